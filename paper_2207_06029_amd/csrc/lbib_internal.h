@@ -1,0 +1,191 @@
+// Internal device-side data of liblbib: job/body tables, window descriptors, kernel
+// argument blocks and the launch functions each translation unit provides.
+//
+// Every kernel walks a device job table, so one lattice, a batch of lattices and the
+// server's resident set all run through the same launches.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbib {
+
+constexpr int Q = 19;
+// Fixed-point scale of the spread body force: contributions are rounded to multiples of 2^-40
+// and summed as 64-bit integers, so the sum does not depend on the order of the atomics.
+constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
+constexpr double FIX_INV = 1.0 / 1099511627776.0;
+constexpr int WIN_MARGIN = 4;    // nodes around a body's bounding box (probe + support + slack)
+constexpr int GROUP = 32;        // lanes that evaluate one MLS point
+constexpr int MLS_PER_BLOCK = 8; // MLS points (32-lane groups) per 256-thread block
+constexpr int MAX_RED_BLOCKS = 65536;
+
+// error flag bits (per job)
+constexpr int FLAG_DOMAIN = 1;     // a support or probe reached a wall node / left the domain
+constexpr int FLAG_WINDOW = 2;     // a body outgrew its reserved window
+constexpr int FLAG_NONFINITE = 4;  // non-finite or runaway density / position / rigid state
+
+// ---------------------------------------------------------------- D3Q19 (Sec. 1.1, Eq. e_i)
+__host__ __device__ constexpr int cx(int i) {
+    return (i == 1 || (i >= 7 && i <= 10)) ? 1 : ((i == 2 || (i >= 11 && i <= 14)) ? -1 : 0);
+}
+__host__ __device__ constexpr int cy(int i) {
+    return (i == 3 || i == 7 || i == 11 || i == 15 || i == 16) ? 1
+         : ((i == 4 || i == 8 || i == 12 || i == 17 || i == 18) ? -1 : 0);
+}
+__host__ __device__ constexpr int cz(int i) {
+    return (i == 5 || i == 9 || i == 13 || i == 15 || i == 17) ? 1
+         : ((i == 6 || i == 10 || i == 14 || i == 16 || i == 18) ? -1 : 0);
+}
+__host__ __device__ constexpr int ce(int i, int a) { return a == 0 ? cx(i) : (a == 1 ? cy(i) : cz(i)); }
+// weights after Eq. (eqfunc): 1/3 rest, 1/18 axis, 1/36 diagonal
+__host__ __device__ constexpr double wq(int i) {
+    return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+__host__ __device__ constexpr int opp(int i) {
+    switch (i) {
+        case 0: return 0;   case 1: return 2;   case 2: return 1;   case 3: return 4;
+        case 4: return 3;   case 5: return 6;   case 6: return 5;   case 7: return 12;
+        case 8: return 11;  case 9: return 14;  case 10: return 13; case 11: return 8;
+        case 12: return 7;  case 13: return 10; case 14: return 9;  case 15: return 18;
+        case 16: return 17; case 17: return 16; default: return 15;
+    }
+}
+constexpr bool table_ok() {
+    for (int i = 0; i < Q; ++i) {
+        for (int a = 0; a < 3; ++a)
+            if (ce(opp(i), a) != -ce(i, a)) return false;
+        int s = (cx(i) != 0) + (cy(i) != 0) + (cz(i) != 0);
+        if ((s == 0) != (i == 0) || (s == 1) != (i >= 1 && i <= 6) || (s == 2) != (i >= 7)) return false;
+    }
+    return true;
+}
+static_assert(table_ok(), "D3Q19 tables inconsistent");
+
+// ---------------------------------------------------------------- tables
+struct JobDev {
+    int nx, ny, nz, storage;
+    long long n;          // nodes
+    long long pop_off;    // element offset of this job's populations in the pool
+    int tile0, ntiles;    // sweep tiles of this job
+    float omega;          // 1 / tau
+    float guo;            // 1 - 1/(2 tau)
+    float nu;             // (tau - 1/2) / 3
+    int zh_axis;          // axis carrying Zou-He walls, -1 if none
+    int bc[6];
+    float wall_u[6][3];
+    float G[3];           // uniform body force density
+    int body0, nbodies;   // bodies living in this lattice
+    int pad0, pad1;
+};
+
+struct WinDesc {
+    int o[3];  // origin node (0 <= o < n along periodic axes)
+    int w[3];  // extent
+};
+
+// A window is usable when 0 <= o < n and 1 <= w <= min(n, cap) on every axis, and on walled
+// axes o + w <= n.  Kernels that walk a window check this first.
+__host__ __device__ inline bool win_valid(const WinDesc& d, const int dims[3], const int cap[3],
+                                          const int bc[6]) {
+    for (int a = 0; a < 3; ++a) {
+        if (d.o[a] < 0 || d.o[a] >= dims[a] || d.w[a] < 1 || d.w[a] > dims[a] || d.w[a] > cap[a])
+            return false;
+        if (bc[2 * a] != 0 && d.o[a] + d.w[a] > dims[a]) return false;
+    }
+    return true;
+}
+
+struct BodyDev {
+    int job, rigid, integrator, nv;
+    int nt, ne, pad0, pad1;
+    long long v0, t0, e0;       // offsets into the vertex, triangle and edge pools
+    long long win_off;          // offset of the body's windows in the window pools (nodes)
+    int win_cap[3];             // reserved window extent per axis
+    int red_slot;               // offset of this body's block partials
+    // CSR of incident elements per vertex, offsets into the incidence pools
+    long long vt_off, ve_off, vh_off;
+    // first block of this body in the centroid / triangle / vertex grids and block counts
+    int blk_c0, nblk_c, blk_t0, nblk_t, blk_v0, nblk_v, pad2, pad3;
+    double kb, kv, mv, V0, mass;
+    double rw, alpha, probe, shell_h;
+    double gravity[3];
+    double Ib[9];               // rigid inertia in the rest frame (about the centroid)
+};
+
+// per-body mutable scalars (device)
+struct BodyState {
+    double V;          // enclosed volume at x^n (deformable)
+    double centre[3];  // vertex mean (deformable) used as torque reference
+    double F[3], M[3]; // hydrodynamic force / torque totals of the last step
+    // rigid body
+    double X[3], R[9], u[3], u1[3], om[3], om1[3];
+    int counter_c, counter_t, counter_v, pad;
+};
+
+// All device pools of one batch.  Kernels take this by value.
+struct Pools {
+    void* popA;
+    void* popB;
+    const JobDev* jobs;
+    const int* tile_job;
+    const BodyDev* bodies;
+    const int* blk_body_c;   // block -> body for the centroid kernel
+    const int* blk_body_t;
+    const int* blk_body_v;
+    double* x;               // [3 nv] positions x^n (all bodies concatenated)
+    double* xprev;           // [3 nv] x^{n-1}
+    double* uv;              // [3 nv] vertex velocity u_v^n
+    double* fv;              // [3 nv] last total vertex force
+    const double* xb;        // [3 nv] rigid rest-frame coordinates
+    const int* tri;          // [3 nt] (vertex indices local to the body)
+    const int* edge;         // [2 ne]
+    const int* hinge;        // [4 ne] x1,x2 (edge, as in triangle 1), x3, x4
+    const double* l0;        // [ne]
+    const double* ks;        // [ne]
+    const double* theta0;    // [ne]
+    const int* vt_ptr;       // [nv+1 per body] incident triangles
+    const int* vt_list;
+    const int* ve_ptr;       // incident edges: 2*edge + (vertex is the second end)
+    const int* ve_list;
+    const int* vh_ptr;       // incident hinges: 4*hinge + role
+    const int* vh_list;
+    double* fext;            // [3 nt] hydrodynamic force per triangle
+    long long* fwin;         // force windows, 3 components x window nodes (fixed point)
+    float4* mwin;            // moment windows (rho - 1, u*)
+    WinDesc* fdesc;          // force-window layout of the current step, per body
+    WinDesc* mdesc;          // layout of the moment window, per body
+    BodyState* bstate;
+    double* partial;         // block partial sums (8 doubles per block)
+    int* flags;              // per job
+};
+
+// ---------------------------------------------------------------- launchers
+struct SweepShape {
+    int block;          // threads per block
+    int npt;            // nodes per thread (block-strided)
+};
+
+// lbib_lattice.hip
+void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int ntiles,
+                  SweepShape shape, hipStream_t s);
+void launch_window_moments(const Pools& P, int storage, bool from_b, int nbodies, int max_cap,
+                           hipStream_t s);
+void launch_macros(const Pools& P, int storage, bool from_b, int job, long long n, float* out4,
+                   hipStream_t s);
+void launch_get_pops(const Pools& P, int storage, bool from_b, int job, long long n, float* out,
+                     hipStream_t s);
+void launch_set_pops(const Pools& P, int storage, bool to_b, int job, long long n,
+                     const double* f, hipStream_t s);
+void launch_init_eq(int job, long long n, const double* rho, const double* u, double* f_out,
+                    hipStream_t s);
+
+// lbib_ib.hip
+void launch_centroids(const Pools& P, int nblocks, hipStream_t s);
+void launch_triangles(const Pools& P, int nblocks, hipStream_t s);
+void launch_vertices(const Pools& P, int nblocks, hipStream_t s);
+
+}  // namespace lbib

@@ -1,0 +1,423 @@
+// Lattice kernels: the fused collide+stream sweep (Sec. 1.1, Eqs. evoleq, eqfunc, forcing),
+// window moments for the immersed boundary, and the state get/set/init kernels.
+//
+// Populations are stored after collision, as deviations g_i = f_i - w_i, structure of arrays
+// [i][z][y][x] per job.  The post-streaming distribution of the current time level is
+// obtained by pulling g_i from x - e_i, with periodic wrap, halfway bounce-back from the
+// node's own opposite population, or the Zou-He closure on wet wall nodes.  Every reader
+// (sweep, moments, getters) uses the same pull, so the post-streaming state is never stored.
+#include "lbib_internal.h"
+
+namespace lbib {
+
+// ---------------------------------------------------------------- storage codecs
+template <typename S> struct Codec;
+template <> struct Codec<float> {
+    __device__ static __forceinline__ float ld(const float* p) { return *p; }
+    __device__ static __forceinline__ void st(float* p, float v) { *p = v; }
+};
+template <> struct Codec<__half> {
+    __device__ static __forceinline__ float ld(const __half* p) { return __half2float(*p); }
+    __device__ static __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v); }
+};
+template <> struct Codec<__hip_bfloat16> {
+    __device__ static __forceinline__ float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+    __device__ static __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+};
+
+// ---------------------------------------------------------------- Zou-He closure
+// Wet wall node on the face of axis a: low face (side 0, inward normal +a) or high face
+// (side 1, inward normal -a).  Unknown populations have e_a == s (s = +1 low, -1 high).
+// Momentum target m = rho u_w - G/2 so that the Guo velocity of the node equals u_w.
+// Written on deviations g = f - w: weights of opposite directions are equal, and the known
+// weights sum to 1 in the density balance.
+__device__ __forceinline__ void zou_he(const JobDev& J, int a, int side, float g[Q]) {
+    const int s = side == 0 ? 1 : -1;
+    const float* uw = J.wall_u[2 * a + side];
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    float sum0 = 0.f, summ = 0.f, t1 = 0.f, t2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ea = ce(i, 0) * (a == 0) + ce(i, 1) * (a == 1) + ce(i, 2) * (a == 2);
+        const int eb1 = ce(i, 0) * (b1 == 0) + ce(i, 1) * (b1 == 1) + ce(i, 2) * (b1 == 2);
+        const int eb2 = ce(i, 0) * (b2 == 0) + ce(i, 1) * (b2 == 1) + ce(i, 2) * (b2 == 2);
+        if (ea == 0) {
+            sum0 += g[i];
+            t1 += g[i] * (float)eb1;
+            t2 += g[i] * (float)eb2;
+        } else if (ea == -s) {
+            summ += g[i];
+        }
+    }
+    const float Ga = J.G[a];
+    const float drho = (sum0 + 2.f * summ - s * 0.5f * Ga + s * uw[a]) / (1.f - s * uw[a]);
+    const float rho = 1.f + drho;
+    const float ma = rho * uw[a] - 0.5f * J.G[a];
+    const float mb1 = rho * uw[b1] - 0.5f * J.G[b1];
+    const float mb2 = rho * uw[b2] - 0.5f * J.G[b2];
+    const float n1 = 0.5f * t1 - mb1 * (1.f / 3.f);
+    const float n2 = 0.5f * t2 - mb2 * (1.f / 3.f);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ea = ce(i, 0) * (a == 0) + ce(i, 1) * (a == 1) + ce(i, 2) * (a == 2);
+        const int eb1 = ce(i, 0) * (b1 == 0) + ce(i, 1) * (b1 == 1) + ce(i, 2) * (b1 == 2);
+        const int eb2 = ce(i, 0) * (b2 == 0) + ce(i, 1) * (b2 == 1) + ce(i, 2) * (b2 == 2);
+        if (ea == s) {
+            const float go = g[opp(i)];
+            if (eb1 == 0 && eb2 == 0)
+                g[i] = go + s * ma * (1.f / 3.f);
+            else if (eb1 != 0)
+                g[i] = go + (s * ma + eb1 * mb1) * (1.f / 6.f) - eb1 * n1;
+            else
+                g[i] = go + (s * ma + eb2 * mb2) * (1.f / 6.f) - eb2 * n2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- pull
+// Post-streaming deviations at node (x, y, z) of job J from the post-collision buffer src.
+template <typename S>
+__device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J, int x, int y,
+                                     int z, long long k, float g[Q]) {
+    const long long N = J.n;
+    const int nx = J.nx, ny = J.ny, nz = J.nz;
+    // source coordinates for e = +1 (c - 1) and e = -1 (c + 1) on each axis
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1, zm = z - 1, zp = z + 1;
+    bool oxm = false, oxp = false, oym = false, oyp = false, ozm = false, ozp = false;
+    if (xm < 0) { if (J.bc[0] == 0) xm += nx; else oxm = true; }
+    if (xp >= nx) { if (J.bc[1] == 0) xp -= nx; else oxp = true; }
+    if (ym < 0) { if (J.bc[2] == 0) ym += ny; else oym = true; }
+    if (yp >= ny) { if (J.bc[3] == 0) yp -= ny; else oyp = true; }
+    if (zm < 0) { if (J.bc[4] == 0) zm += nz; else ozm = true; }
+    if (zp >= nz) { if (J.bc[5] == 0) zp -= nz; else ozp = true; }
+    bool unknown = false;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int e0 = cx(i), e1 = cy(i), e2 = cz(i);
+        const int sx = e0 == 1 ? xm : (e0 == -1 ? xp : x);
+        const int sy = e1 == 1 ? ym : (e1 == -1 ? yp : y);
+        const int sz = e2 == 1 ? zm : (e2 == -1 ? zp : z);
+        const bool o0 = e0 == 1 ? oxm : (e0 == -1 ? oxp : false);
+        const bool o1 = e1 == 1 ? oym : (e1 == -1 ? oyp : false);
+        const bool o2 = e2 == 1 ? ozm : (e2 == -1 ? ozp : false);
+        if (!(o0 || o1 || o2)) {
+            g[i] = Codec<S>::ld(src + (long long)i * N + (long long)sx +
+                                (long long)nx * ((long long)sy + (long long)ny * sz));
+        } else {
+            const int f0 = o0 ? (e0 == 1 ? 0 : 1) : -1;
+            const int f1 = o1 ? (e1 == 1 ? 2 : 3) : -1;
+            const int f2 = o2 ? (e2 == 1 ? 4 : 5) : -1;
+            const int ff = f0 >= 0 ? f0 : (f1 >= 0 ? f1 : f2);
+            if (J.bc[ff] == 2) {
+                float uwx = 0.f, uwy = 0.f, uwz = 0.f;
+                if (f0 >= 0) { uwx += J.wall_u[f0][0]; uwy += J.wall_u[f0][1]; uwz += J.wall_u[f0][2]; }
+                if (f1 >= 0) { uwx += J.wall_u[f1][0]; uwy += J.wall_u[f1][1]; uwz += J.wall_u[f1][2]; }
+                if (f2 >= 0) { uwx += J.wall_u[f2][0]; uwy += J.wall_u[f2][1]; uwz += J.wall_u[f2][2]; }
+                const float eu = e0 * uwx + e1 * uwy + e2 * uwz;
+                g[i] = Codec<S>::ld(src + (long long)opp(i) * N + k) + (float)(6.0 * wq(i)) * eu;
+            } else {
+                g[i] = 0.f;
+                unknown = true;
+            }
+        }
+    }
+    if (unknown) {
+        const int a = J.zh_axis;
+        const int c = a == 0 ? x : (a == 1 ? y : z);
+        zou_he(J, a, c == 0 ? 0 : 1, g);
+    }
+}
+
+__device__ __forceinline__ void node_coords(const JobDev& J, long long k, int& x, int& y, int& z) {
+    const unsigned kk = (unsigned)k;
+    const unsigned nx = (unsigned)J.nx, ny = (unsigned)J.ny;
+    const unsigned q = kk / nx;
+    x = (int)(kk - q * nx);
+    z = (int)(q / ny);
+    y = (int)(q - (unsigned)z * ny);
+}
+
+// Body force at a node: uniform G plus the fixed-point immersed-boundary force of every body
+// of the job whose force window holds the node.
+__device__ __forceinline__ void node_force(const Pools& P, const JobDev& J, int x, int y, int z,
+                                           float F[3]) {
+    F[0] = J.G[0]; F[1] = J.G[1]; F[2] = J.G[2];
+    for (int b = J.body0; b < J.body0 + J.nbodies; ++b) {
+        const WinDesc d = P.fdesc[b];
+        const BodyDev& B = P.bodies[b];
+        const int dims[3] = {J.nx, J.ny, J.nz};
+        if (!win_valid(d, dims, B.win_cap, J.bc)) continue;
+        int lx = x - d.o[0], ly = y - d.o[1], lz = z - d.o[2];
+        if (lx < 0) lx += J.nx;
+        if (ly < 0) ly += J.ny;
+        if (lz < 0) lz += J.nz;
+        if (lx < d.w[0] && ly < d.w[1] && lz < d.w[2]) {
+            const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+            const long long l = lx + (long long)d.w[0] * (ly + (long long)d.w[1] * lz);
+            const long long* fw = P.fwin + 3 * B.win_off + l;
+            F[0] += (float)((double)fw[0] * FIX_INV);
+            F[1] += (float)((double)fw[capn] * FIX_INV);
+            F[2] += (float)((double)fw[2 * capn] * FIX_INV);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- fused sweep
+// One node: pull, moments, body force, BGK collision with Guo forcing (all on deviations),
+// store.  With COLLIDE false the pulled values are stored unchanged (pure streaming).
+template <typename S, bool COLLIDE>
+__device__ __forceinline__ void sweep_node(const Pools& P, const JobDev& J, const S* __restrict__ src,
+                                           S* __restrict__ dst, long long k, int job) {
+    int x, y, z;
+    node_coords(J, k, x, y, z);
+    float g[Q];
+    pull<S>(src, J, x, y, z, k, g);
+    const long long N = J.n;
+    if (COLLIDE) {
+        float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            drho += g[i];
+            if (cx(i)) jx += cx(i) * g[i];
+            if (cy(i)) jy += cy(i) * g[i];
+            if (cz(i)) jz += cz(i) * g[i];
+        }
+        float F[3];
+        if (J.nbodies) node_force(P, J, x, y, z, F);
+        else { F[0] = J.G[0]; F[1] = J.G[1]; F[2] = J.G[2]; }
+        const float rho = 1.f + drho;
+        const float ir = 1.f / rho;
+        const float ux = (jx + 0.5f * F[0]) * ir;
+        const float uy = (jy + 0.5f * F[1]) * ir;
+        const float uz = (jz + 0.5f * F[2]) * ir;
+        const float uu = ux * ux + uy * uy + uz * uz;
+        const float uF = ux * F[0] + uy * F[1] + uz * F[2];
+        const float om = J.omega, gk = J.guo;
+        if (!(fabsf(drho) < 0.5f)) atomicOr(P.flags + job, FLAG_NONFINITE);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float w = (float)wq(i);
+            const float eu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+            const float eF = cx(i) * F[0] + cy(i) * F[1] + cz(i) * F[2];
+            const float geq = w * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+            const float Fi = gk * w * (3.f * (eF - uF) + 9.f * eu * eF);
+            Codec<S>::st(dst + (long long)i * N + k, g[i] - om * (g[i] - geq) + Fi);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) Codec<S>::st(dst + (long long)i * N + k, g[i]);
+    }
+}
+
+template <typename S, bool COLLIDE, int NPT>
+__global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b) {
+    const int tile = blockIdx.x;
+    const int job = P.tile_job[tile];
+    const JobDev& J = P.jobs[job];
+    const S* src = (const S*)(a_to_b ? P.popA : P.popB) + J.pop_off;
+    S* dst = (S*)(a_to_b ? P.popB : P.popA) + J.pop_off;
+    const long long base = (long long)(tile - J.tile0) * blockDim.x * NPT;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const long long k = base + (long long)r * blockDim.x + threadIdx.x;
+        if (k < J.n) sweep_node<S, COLLIDE>(P, J, src, dst, k, job);
+    }
+}
+
+template <typename S, bool C>
+static void sweep_t(const Pools& P, bool a_to_b, int ntiles, SweepShape sh, hipStream_t s) {
+    dim3 grid(ntiles), block(sh.block);
+    switch (sh.npt) {
+        case 1: hipLaunchKernelGGL((k_sweep<S, C, 1>), grid, block, 0, s, P, (int)a_to_b); break;
+        case 2: hipLaunchKernelGGL((k_sweep<S, C, 2>), grid, block, 0, s, P, (int)a_to_b); break;
+        default: hipLaunchKernelGGL((k_sweep<S, C, 4>), grid, block, 0, s, P, (int)a_to_b); break;
+    }
+}
+
+void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int ntiles,
+                  SweepShape shape, hipStream_t s) {
+    if (ntiles <= 0) return;
+    if (storage == 0) collide ? sweep_t<float, true>(P, a_to_b, ntiles, shape, s)
+                              : sweep_t<float, false>(P, a_to_b, ntiles, shape, s);
+    else if (storage == 1) collide ? sweep_t<__half, true>(P, a_to_b, ntiles, shape, s)
+                                   : sweep_t<__half, false>(P, a_to_b, ntiles, shape, s);
+    else collide ? sweep_t<__hip_bfloat16, true>(P, a_to_b, ntiles, shape, s)
+                 : sweep_t<__hip_bfloat16, false>(P, a_to_b, ntiles, shape, s);
+}
+
+// ---------------------------------------------------------------- window moments
+// For every node of a body's current window: pull the post-streaming state, store
+// (rho - 1, u*) with u* = sum f e / rho, and clear the force window for the next step.
+template <typename S>
+__global__ void __launch_bounds__(256) k_window_moments(Pools P, int from_b) {
+    const int b = blockIdx.y;
+    const BodyDev& B = P.bodies[b];
+    const JobDev& J = P.jobs[B.job];
+    const WinDesc d = P.fdesc[b];
+    const int dims[3] = {J.nx, J.ny, J.nz};
+    if (!win_valid(d, dims, B.win_cap, J.bc)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(P.flags + B.job, FLAG_WINDOW);
+        return;
+    }
+    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.mdesc[b] = d;
+    const long long nw = (long long)d.w[0] * d.w[1] * d.w[2];
+    if (l >= nw) return;
+    const int lx = (int)(l % d.w[0]);
+    const int ly = (int)((l / d.w[0]) % d.w[1]);
+    const int lz = (int)(l / ((long long)d.w[0] * d.w[1]));
+    int x = d.o[0] + lx, y = d.o[1] + ly, z = d.o[2] + lz;
+    if (x >= J.nx) x -= J.nx;
+    if (y >= J.ny) y -= J.ny;
+    if (z >= J.nz) z -= J.nz;
+    const long long k = x + (long long)J.nx * (y + (long long)J.ny * z);
+    const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
+    float g[Q];
+    pull<S>(src, J, x, y, z, k, g);
+    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += g[i];
+        jx += cx(i) * g[i];
+        jy += cy(i) * g[i];
+        jz += cz(i) * g[i];
+    }
+    const float ir = 1.f / (1.f + drho);
+    P.mwin[B.win_off + l] = make_float4(drho, jx * ir, jy * ir, jz * ir);
+    const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+    long long* fw = P.fwin + 3 * B.win_off + l;
+    fw[0] = 0;
+    fw[capn] = 0;
+    fw[2 * capn] = 0;
+}
+
+void launch_window_moments(const Pools& P, int storage, bool from_b, int nbodies, int max_cap,
+                           hipStream_t s) {
+    if (nbodies <= 0) return;
+    dim3 grid((max_cap + 255) / 256, nbodies), block(256);
+    if (storage == 0) hipLaunchKernelGGL(k_window_moments<float>, grid, block, 0, s, P, (int)from_b);
+    else if (storage == 1) hipLaunchKernelGGL(k_window_moments<__half>, grid, block, 0, s, P, (int)from_b);
+    else hipLaunchKernelGGL(k_window_moments<__hip_bfloat16>, grid, block, 0, s, P, (int)from_b);
+}
+
+// ---------------------------------------------------------------- getters / setters
+template <typename S>
+__global__ void k_macros(Pools P, int from_b, int job, float4* out) {
+    const JobDev& J = P.jobs[job];
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= J.n) return;
+    int x, y, z;
+    node_coords(J, k, x, y, z);
+    const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
+    float g[Q];
+    pull<S>(src, J, x, y, z, k, g);
+    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += g[i];
+        jx += cx(i) * g[i];
+        jy += cy(i) * g[i];
+        jz += cz(i) * g[i];
+    }
+    const float ir = 1.f / (1.f + drho);
+    out[k] = make_float4(drho, jx * ir, jy * ir, jz * ir);
+}
+
+template <typename S>
+__global__ void k_get_pops(Pools P, int from_b, int job, float* out) {
+    const JobDev& J = P.jobs[job];
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= J.n) return;
+    int x, y, z;
+    node_coords(J, k, x, y, z);
+    const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
+    float g[Q];
+    pull<S>(src, J, x, y, z, k, g);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[(long long)i * J.n + k] = g[i];
+}
+
+// Inverse of the pull: write the post-collision entries whose pull reproduces f.  Entries
+// pulled from behind a Zou-He face are not representable; the closure rebuilds them.
+template <typename S>
+__global__ void k_set_pops(Pools P, int to_b, int job, const double* f) {
+    const JobDev& J = P.jobs[job];
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= J.n) return;
+    int x, y, z;
+    node_coords(J, k, x, y, z);
+    S* dst = (S*)(to_b ? P.popB : P.popA) + J.pop_off;
+    const int n[3] = {J.nx, J.ny, J.nz};
+    const int c[3] = {x, y, z};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float gi = (float)(f[(long long)i * J.n + k] - wq(i));
+        int s[3];
+        int face = -1, nout = 0;
+        float uw[3] = {0.f, 0.f, 0.f};
+        bool zh = false;
+        for (int a = 0; a < 3; ++a) {
+            s[a] = c[a] - ce(i, a);
+            if (s[a] < 0 || s[a] >= n[a]) {
+                const int fa = 2 * a + (s[a] < 0 ? 0 : 1);
+                if (J.bc[fa] == 0) {
+                    s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
+                } else {
+                    ++nout;
+                    if (face < 0) face = fa;
+                    if (J.bc[fa] == 1) zh = true;
+                    uw[0] += J.wall_u[fa][0]; uw[1] += J.wall_u[fa][1]; uw[2] += J.wall_u[fa][2];
+                }
+            }
+        }
+        if (nout == 0) {
+            Codec<S>::st(dst + (long long)i * J.n + s[0] + (long long)n[0] * (s[1] + (long long)n[1] * s[2]), gi);
+        } else if (!zh && J.bc[face] == 2) {
+            const float eu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
+            Codec<S>::st(dst + (long long)opp(i) * J.n + k, gi - (float)(6.0 * wq(i)) * eu);
+        }
+    }
+}
+
+// Equilibrium Eq. (eqfunc) of given rho, u, in double, as post-streaming populations.
+__global__ void k_init_eq(long long n, const double* rho, const double* u, double* f) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double r = rho ? rho[k] : 1.0;
+    const double ux = u ? u[k] : 0.0, uy = u ? u[n + k] : 0.0, uz = u ? u[2 * n + k] : 0.0;
+    const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double eu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+        f[(long long)i * n + k] = wq(i) * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+}
+
+#define LBIB_DISPATCH(storage, KERNEL, grid, block, s, ...)                                   \
+    do {                                                                                    \
+        if ((storage) == 0) hipLaunchKernelGGL(KERNEL<float>, grid, block, 0, s, __VA_ARGS__); \
+        else if ((storage) == 1) hipLaunchKernelGGL(KERNEL<__half>, grid, block, 0, s, __VA_ARGS__); \
+        else hipLaunchKernelGGL(KERNEL<__hip_bfloat16>, grid, block, 0, s, __VA_ARGS__);    \
+    } while (0)
+
+void launch_macros(const Pools& P, int storage, bool from_b, int job, long long n, float* out4,
+                   hipStream_t s) {
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    LBIB_DISPATCH(storage, k_macros, grid, block, s, P, (int)from_b, job, (float4*)out4);
+}
+void launch_get_pops(const Pools& P, int storage, bool from_b, int job, long long n, float* out,
+                     hipStream_t s) {
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    LBIB_DISPATCH(storage, k_get_pops, grid, block, s, P, (int)from_b, job, out);
+}
+void launch_set_pops(const Pools& P, int storage, bool to_b, int job, long long n,
+                     const double* f, hipStream_t s) {
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    LBIB_DISPATCH(storage, k_set_pops, grid, block, s, P, (int)to_b, job, f);
+}
+void launch_init_eq(int, long long n, const double* rho, const double* u, double* f, hipStream_t s) {
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_init_eq, grid, block, 0, s, n, rho, u, f);
+}
+
+}  // namespace lbib

@@ -1,0 +1,117 @@
+// Host-side types of the runtime: device arena, host copy of a body, and the Batch that owns
+// all device pools of a set of lattices.
+#pragma once
+
+#include "lbib.h"
+#include "lbib_internal.h"
+
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace lbib {
+
+lbib_status fail(lbib_status code, const std::string& msg);
+const char* last_error();
+lbib_status check_lattice(const lbib_lattice_desc& d);
+size_t storage_bytes(int storage);
+
+// Device memory: a caller workspace carved by a bump pointer, or hipMalloc'd blocks.
+struct Arena {
+    void* base = nullptr;
+    size_t cap = 0, used = 0, total = 0;
+    std::vector<void*> owned;
+    lbib_status alloc(size_t bytes, void** out);
+    void release_from(size_t mark_used, size_t mark_owned);
+    ~Arena();
+};
+
+struct HostBody {
+    lbib_body_desc desc{};
+    int job = 0, local_id = 0;
+    int nv = 0, nt = 0, ne = 0;
+    std::vector<double> x, xprev, uv, fv, xb;
+    std::vector<int> tri, edge, hinge;
+    std::vector<double> l0, ks, theta0;
+    std::vector<int> vt_ptr, vt_list, ve_ptr, ve_list, vh_ptr, vh_list;
+    double V0 = 0, S0 = 0, mv = 0, mass = 0, rbound = 0;
+    double X0[3] = {0, 0, 0};
+    double Ib[9] = {0};
+    bool has_state = false;   // state below holds device values to restore after a rebuild
+    BodyState state{};
+    WinDesc fdesc{};
+};
+
+lbib_status build_body(const lbib_body_desc& d, const double* xyz, int nv, const int* tri, int nt,
+                       HostBody& hb);
+
+struct Batch {
+    hipStream_t stream = nullptr;
+    int storage = 0;
+    Arena arena;
+    size_t mark_used = 0, mark_owned = 0;
+    std::vector<lbib_lattice_desc> ldesc;
+    std::vector<JobDev> jobs;
+    std::vector<int> tile_job;
+    int* d_tile_job = nullptr;
+    size_t tile_cap = 0;
+    JobDev* d_jobs = nullptr;
+    BodyDev* d_bodies = nullptr;
+    long long pop_elems = 0;
+    std::vector<HostBody> hbodies;
+    std::vector<BodyDev> host_bodies;
+    int nbodies = 0;
+    int nblk_c = 0, nblk_t = 0, nblk_v = 0;
+    long long max_cap = 0, max_red = 0;
+    Pools P{};
+    bool cur_b = false;        // buffer holding the latest post-collision state
+    bool primed = false;       // moment windows hold the moments of the current state
+    long long step_count = 0;
+    SweepShape shape{256, 1};
+    bool use_graph = false;
+    bool graph_valid = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_events, step_events;
+    long long step_event_steps = 0;
+
+    void job_from_desc(const lbib_lattice_desc& d, JobDev& J);
+    lbib_status create_lattices(const std::vector<lbib_lattice_desc>& descs, int storage,
+                                void* stream, void* ws, size_t ws_bytes,
+                                const std::vector<char>* skip_init = nullptr);
+    lbib_status retile();
+    lbib_status set_shape(SweepShape s);
+    lbib_status rebuild_bodies();
+    lbib_status download_body_state();
+    lbib_status add_body(int job, const lbib_body_desc& d, const double* xyz, int nv,
+                         const int* tri, int nt, int* id);
+    int body_index(int job, int local) const;
+    lbib_status init_job(int job, const double* rho, const double* u);
+    lbib_status set_populations(int job, const double* f);
+    lbib_status get_macros(int job, double* rho, double* u);
+    lbib_status get_populations(int job, double* f);
+    lbib_status check_flags();
+    lbib_status job_flags(std::vector<int>& fl);
+    lbib_status prime();
+    lbib_status enqueue_step(bool collide);
+    lbib_status step(int nsteps, bool collide);
+    lbib_status capture_graph();
+    lbib_status kernel_time(int kernel, double* ms, int64_t* count);
+    void clear_events();
+    lbib_status body_state(int bi, double* xyz, double* vel);
+    lbib_status body_forces(int bi, double* fv, double* F, double* M);
+    lbib_status body_set_velocity(int bi, const double* v);
+    size_t device_bytes() const;
+    ~Batch();
+};
+
+}  // namespace lbib
+
+// Handles handed out through the C ABI.
+struct lbib_lattice {
+    lbib::Batch* batch = nullptr;
+    int job = 0;
+    bool owner = false;
+};

@@ -1,0 +1,856 @@
+// Host runtime behind the C ABI of include/lbib.h: device pools of a batch of lattices,
+// rest state of immersed bodies, the per-step launch sequence, getters and setters, and
+// kernel timing.  A single lattice is a batch of one job.
+#include "lbib.h"
+#include "lbib_internal.h"
+#include "lbib_runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace lbib {
+
+static thread_local std::string g_err;
+lbib_status fail(lbib_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+const char* last_error() { return g_err.c_str(); }
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) return fail(LBIB_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- device allocation
+lbib_status Arena::alloc(size_t bytes, void** out) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    if (base) {
+        if (used + bytes > cap) return fail(LBIB_ENOMEM, "workspace too small");
+        *out = (char*)base + used;
+        used += bytes;
+        return LBIB_OK;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(LBIB_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    owned.push_back(p);
+    *out = p;
+    total += bytes;
+    return LBIB_OK;
+}
+void Arena::release_from(size_t mark_used, size_t mark_owned) {
+    if (base) { used = mark_used; return; }
+    while (owned.size() > mark_owned) {
+        hipFree(owned.back());
+        owned.pop_back();
+    }
+}
+Arena::~Arena() {
+    if (!base)
+        for (void* p : owned) hipFree(p);
+}
+
+template <typename T>
+static lbib_status upload(Arena& A, const std::vector<T>& v, T** out, hipStream_t s) {
+    void* p;
+    lbib_status st = A.alloc(sizeof(T) * std::max<size_t>(v.size(), 1), &p);
+    if (st) return st;
+    if (!v.empty()) HIP_TRY(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    *out = (T*)p;
+    return LBIB_OK;
+}
+
+// ---------------------------------------------------------------- validation
+size_t storage_bytes(int storage) { return storage == 0 ? 4 : 2; }
+
+lbib_status check_lattice(const lbib_lattice_desc& d) {
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(LBIB_EINVAL, "lattice dimensions must be >= 1");
+    if ((long long)d.nx * d.ny * d.nz >= (1LL << 31)) return fail(LBIB_EINVAL, "lattice too large");
+    if (!(d.tau > 0.5)) return fail(LBIB_EINVAL, "tau must exceed 1/2");
+    if (d.storage < 0 || d.storage > 2) return fail(LBIB_EINVAL, "unknown storage");
+    int zh = -1, moving = 0;
+    const int n[3] = {d.nx, d.ny, d.nz};
+    for (int a = 0; a < 3; ++a) {
+        const int lo = d.bc[2 * a], hi = d.bc[2 * a + 1];
+        if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return fail(LBIB_EINVAL, "unknown boundary kind");
+        if ((lo == 0) != (hi == 0)) return fail(LBIB_EINVAL, "a periodic face needs a periodic partner");
+        if (lo == 1 || hi == 1) {
+            if (zh >= 0) return fail(LBIB_EINVAL, "Zou-He walls on one axis only");
+            zh = a;
+            if (n[a] < 3) return fail(LBIB_EINVAL, "a Zou-He axis needs at least 3 nodes");
+        }
+        for (int s = 0; s < 2; ++s)
+            if (d.bc[2 * a + s] == 2 && (d.wall_u[2 * a + s][0] != 0 || d.wall_u[2 * a + s][1] != 0 ||
+                                         d.wall_u[2 * a + s][2] != 0))
+                moving |= 1 << a;
+    }
+    if (zh >= 0)
+        for (int a = 0; a < 3; ++a)
+            if (a != zh && d.bc[2 * a] != 0) return fail(LBIB_EINVAL, "Zou-He walls need periodic tangential axes");
+    if (moving & (moving - 1)) return fail(LBIB_EINVAL, "moving bounce-back walls on one axis only");
+    return LBIB_OK;
+}
+
+// ---------------------------------------------------------------- body rest state (a0)
+static void vsub(const double* a, const double* b, double* c) { for (int i = 0; i < 3; ++i) c[i] = a[i] - b[i]; }
+static void vcross(const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double vdot(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static double hinge_angle(const double* x, const int* h) {
+    double e[3], p3[3], p4[3], q[3], N1[3], N2[3], c[3];
+    vsub(x + 3 * h[1], x + 3 * h[0], e);
+    vsub(x + 3 * h[2], x + 3 * h[0], p3);
+    vsub(x + 3 * h[3], x + 3 * h[1], p4);
+    vsub(x + 3 * h[0], x + 3 * h[1], q);
+    vcross(e, p3, N1);
+    vcross(q, p4, N2);
+    const double a1 = std::sqrt(vdot(N1, N1)), a2 = std::sqrt(vdot(N2, N2)), le = std::sqrt(vdot(e, e));
+    double n1[3] = {N1[0] / a1, N1[1] / a1, N1[2] / a1}, n2[3] = {N2[0] / a2, N2[1] / a2, N2[2] / a2};
+    vcross(n1, n2, c);
+    return std::atan2(vdot(c, e) / le, vdot(n1, n2));
+}
+
+// Build topology and rest state of one body.  Returns EINVAL for meshes that are not closed,
+// consistently oriented, outward 2-manifolds.
+lbib_status build_body(const lbib_body_desc& d, const double* xyz, int nv, const int* tri, int nt,
+                       HostBody& hb) {
+    if (nv < 4 || nt < 4) return fail(LBIB_EINVAL, "mesh too small");
+    if (!(d.mls_rw > 0) || !(d.mls_alpha > 0) || !(d.probe_len >= 0) || !(d.shell_h > 0))
+        return fail(LBIB_EINVAL, "bad MLS / probe / shell parameters");
+    if (!(d.mass_ratio > 0)) return fail(LBIB_EINVAL, "mass ratio must be positive");
+    if (d.integrator != 0 && d.integrator != 1) return fail(LBIB_EINVAL, "unknown integrator");
+    if (!d.rigid && (d.gravity[0] != 0 || d.gravity[1] != 0 || d.gravity[2] != 0))
+        return fail(LBIB_EINVAL, "gravity is supported on rigid bodies only");
+    for (int i = 0; i < 3 * nt; ++i)
+        if (tri[i] < 0 || tri[i] >= nv) return fail(LBIB_EINVAL, "triangle index out of range");
+    for (int i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(xyz[i])) return fail(LBIB_EINVAL, "non-finite vertex");
+    hb = HostBody();
+    hb.desc = d;
+    hb.nv = nv;
+    hb.nt = nt;
+    hb.x.assign(xyz, xyz + 3 * nv);
+    hb.tri.assign(tri, tri + 3 * nt);
+    // half-edges keyed by (vmin, vmax); the owning triangle and direction follow
+    struct HE { long long key; int t, fwd; };
+    std::vector<HE> he(3 * (size_t)nt);
+    for (int t = 0; t < nt; ++t)
+        for (int j = 0; j < 3; ++j) {
+            const int a = tri[3 * t + j], b = tri[3 * t + (j + 1) % 3];
+            if (a == b) return fail(LBIB_EINVAL, "degenerate triangle");
+            he[3 * t + j] = {(long long)std::min(a, b) * nv + std::max(a, b), t, a < b ? 1 : 0};
+        }
+    std::sort(he.begin(), he.end(), [](const HE& p, const HE& q) {
+        return p.key != q.key ? p.key < q.key : p.t < q.t;
+    });
+    if (he.size() % 2) return fail(LBIB_EINVAL, "mesh is not closed");
+    const int ne = (int)he.size() / 2;
+    hb.ne = ne;
+    hb.edge.resize(2 * (size_t)ne);
+    hb.hinge.resize(4 * (size_t)ne);
+    std::vector<int> etri(2 * (size_t)ne);
+    for (int e = 0; e < ne; ++e) {
+        const HE& p = he[2 * e];
+        const HE& q = he[2 * e + 1];
+        const bool dup = (2 * e + 2 < (int)he.size() && he[2 * e + 2].key == p.key);
+        if (p.key != q.key || p.fwd == q.fwd || dup)
+            return fail(LBIB_EINVAL, "mesh is not a closed, consistently oriented 2-manifold");
+        const int v1 = (int)(p.key / nv), v2 = (int)(p.key % nv);
+        hb.edge[2 * e] = v1;
+        hb.edge[2 * e + 1] = v2;
+        // triangle 1 traverses v1 -> v2
+        const int t1 = p.fwd ? p.t : q.t, t2 = p.fwd ? q.t : p.t;
+        etri[2 * e] = t1;
+        etri[2 * e + 1] = t2;
+        int o3 = -1, o4 = -1;
+        for (int j = 0; j < 3; ++j) {
+            if (tri[3 * t1 + j] != v1 && tri[3 * t1 + j] != v2) o3 = tri[3 * t1 + j];
+            if (tri[3 * t2 + j] != v1 && tri[3 * t2 + j] != v2) o4 = tri[3 * t2 + j];
+        }
+        hb.hinge[4 * e] = v1; hb.hinge[4 * e + 1] = v2; hb.hinge[4 * e + 2] = o3; hb.hinge[4 * e + 3] = o4;
+    }
+    // areas, volume (about vertex 0), surface
+    std::vector<double> A(nt);
+    double S0 = 0.0, V0 = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        double ab[3], ac[3], N[3], pa[3], pb[3], pc[3], bc[3];
+        vsub(xyz + 3 * tri[3 * t + 1], xyz + 3 * tri[3 * t], ab);
+        vsub(xyz + 3 * tri[3 * t + 2], xyz + 3 * tri[3 * t], ac);
+        vcross(ab, ac, N);
+        A[t] = 0.5 * std::sqrt(vdot(N, N));
+        S0 += A[t];
+        vsub(xyz + 3 * tri[3 * t], xyz, pa);
+        vsub(xyz + 3 * tri[3 * t + 1], xyz, pb);
+        vsub(xyz + 3 * tri[3 * t + 2], xyz, pc);
+        vcross(pb, pc, bc);
+        V0 += vdot(pa, bc) / 6.0;
+    }
+    if (!(V0 > 0)) return fail(LBIB_EINVAL, "mesh is not outward oriented");
+    hb.V0 = V0;
+    hb.S0 = S0;
+    hb.l0.resize(ne);
+    hb.ks.resize(ne);
+    hb.theta0.resize(ne);
+    for (int e = 0; e < ne; ++e) {
+        double r[3];
+        vsub(xyz + 3 * hb.edge[2 * e], xyz + 3 * hb.edge[2 * e + 1], r);
+        hb.l0[e] = std::sqrt(vdot(r, r));
+        // Van Gelder surface weighting with the rest areas (Sec. 1.3)
+        hb.ks[e] = d.ks0 * d.thickness * (A[etri[2 * e]] + A[etri[2 * e + 1]]) / (hb.l0[e] * hb.l0[e]);
+        hb.theta0[e] = hinge_angle(xyz, &hb.hinge[4 * e]);
+    }
+    hb.mv = d.mass_ratio * d.thickness * S0 / nv;
+    // incidence lists (CSR) per vertex
+    hb.vt_ptr.assign(nv + 1, 0);
+    hb.ve_ptr.assign(nv + 1, 0);
+    hb.vh_ptr.assign(nv + 1, 0);
+    for (int t = 0; t < nt; ++t) for (int j = 0; j < 3; ++j) hb.vt_ptr[tri[3 * t + j] + 1]++;
+    for (int e = 0; e < ne; ++e) {
+        hb.ve_ptr[hb.edge[2 * e] + 1]++;
+        hb.ve_ptr[hb.edge[2 * e + 1] + 1]++;
+        for (int r = 0; r < 4; ++r) hb.vh_ptr[hb.hinge[4 * e + r] + 1]++;
+    }
+    for (int v = 0; v < nv; ++v) {
+        hb.vt_ptr[v + 1] += hb.vt_ptr[v];
+        hb.ve_ptr[v + 1] += hb.ve_ptr[v];
+        hb.vh_ptr[v + 1] += hb.vh_ptr[v];
+    }
+    hb.vt_list.resize(hb.vt_ptr[nv]);
+    hb.ve_list.resize(hb.ve_ptr[nv]);
+    hb.vh_list.resize(hb.vh_ptr[nv]);
+    {
+        std::vector<int> ft(hb.vt_ptr.begin(), hb.vt_ptr.end() - 1), fe(hb.ve_ptr.begin(), hb.ve_ptr.end() - 1),
+            fh(hb.vh_ptr.begin(), hb.vh_ptr.end() - 1);
+        for (int t = 0; t < nt; ++t) for (int j = 0; j < 3; ++j) hb.vt_list[ft[tri[3 * t + j]]++] = t;
+        for (int e = 0; e < ne; ++e) {
+            hb.ve_list[fe[hb.edge[2 * e]]++] = 2 * e;
+            hb.ve_list[fe[hb.edge[2 * e + 1]]++] = 2 * e + 1;
+            for (int r = 0; r < 4; ++r) hb.vh_list[fh[hb.hinge[4 * e + r]]++] = 4 * e + r;
+        }
+    }
+    // rigid mass properties: signed tetrahedra from the origin, then second moments about the
+    // volume centroid; inertia I = rho_s (tr(C) 1 - C)
+    double X0[3] = {0, 0, 0}, C[9] = {0};
+    {
+        double vol = 0.0, m1[3] = {0, 0, 0};
+        for (int t = 0; t < nt; ++t) {
+            const double *a = xyz + 3 * tri[3 * t], *b = xyz + 3 * tri[3 * t + 1], *c = xyz + 3 * tri[3 * t + 2];
+            double bc[3];
+            vcross(b, c, bc);
+            const double vt = vdot(a, bc) / 6.0;
+            vol += vt;
+            for (int i = 0; i < 3; ++i) m1[i] += vt * (a[i] + b[i] + c[i]) / 4.0;
+        }
+        for (int i = 0; i < 3; ++i) X0[i] = m1[i] / vol;
+        for (int t = 0; t < nt; ++t) {
+            double p[3][3];
+            for (int j = 0; j < 3; ++j) vsub(xyz + 3 * tri[3 * t + j], X0, p[j]);
+            double bc[3];
+            vcross(p[1], p[2], bc);
+            const double vt = vdot(p[0], bc) / 6.0;
+            double s[3] = {p[0][0] + p[1][0] + p[2][0], p[0][1] + p[1][1] + p[2][1], p[0][2] + p[1][2] + p[2][2]};
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    C[3 * i + j] += vt / 20.0 * (p[0][i] * p[0][j] + p[1][i] * p[1][j] + p[2][i] * p[2][j] + s[i] * s[j]);
+        }
+    }
+    const double tr = C[0] + C[4] + C[8];
+    for (int i = 0; i < 9; ++i) hb.Ib[i] = d.mass_ratio * ((i % 4 == 0 ? tr : 0.0) - C[i]);
+    hb.mass = d.mass_ratio * V0;
+    for (int i = 0; i < 3; ++i) hb.X0[i] = X0[i];
+    hb.xb.resize(3 * (size_t)nv);
+    double rb = 0.0;
+    for (int v = 0; v < nv; ++v) {
+        double r[3];
+        vsub(xyz + 3 * v, X0, r);
+        for (int i = 0; i < 3; ++i) hb.xb[3 * v + i] = r[i];
+        rb = std::max(rb, std::sqrt(vdot(r, r)));
+    }
+    hb.rbound = rb;
+    hb.xprev = hb.x;
+    hb.uv.assign(3 * (size_t)nv, 0.0);
+    return LBIB_OK;
+}
+
+// Window descriptor from a bounding box (same rule as the device code).
+static WinDesc window_for(const JobDev& J, const double lo[3], const double hi[3], const int cap[3], bool* over) {
+    WinDesc d;
+    const int dims[3] = {J.nx, J.ny, J.nz};
+    *over = false;
+    for (int a = 0; a < 3; ++a) {
+        int l = (int)std::floor(lo[a]) - WIN_MARGIN, h = (int)std::ceil(hi[a]) + WIN_MARGIN;
+        if (J.bc[2 * a] == 0) {
+            const int w = h - l + 1;
+            if (w >= dims[a]) { d.o[a] = 0; d.w[a] = dims[a]; }
+            else { int o = l % dims[a]; if (o < 0) o += dims[a]; d.o[a] = o; d.w[a] = w; }
+        } else {
+            l = std::max(l, 0);
+            h = std::min(h, dims[a] - 1);
+            d.o[a] = l;
+            d.w[a] = h >= l ? h - l + 1 : 1;
+        }
+        if (d.w[a] > cap[a]) { *over = true; d.w[a] = cap[a]; }
+    }
+    return d;
+}
+
+// Supports and probes of a body at positions x must stay off wall nodes.
+static lbib_status check_support(const JobDev& J, const HostBody& hb) {
+    const double reach = hb.desc.probe_len + hb.desc.mls_rw + 0.5;
+    const int dims[3] = {J.nx, J.ny, J.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (J.bc[2 * a] == 0) continue;
+        const double lo = J.bc[2 * a] == 1 ? 1.0 : 0.0, hi = J.bc[2 * a] == 1 ? dims[a] - 2.0 : dims[a] - 1.0;
+        for (int v = 0; v < hb.nv; ++v) {
+            const double c = hb.x[3 * v + a];
+            if (c - reach < lo - 0.5 || c + reach > hi + 0.5)
+                return fail(LBIB_EDOMAIN, "body support or probe reaches a wall");
+        }
+    }
+    return LBIB_OK;
+}
+
+// ---------------------------------------------------------------- batch construction
+void Batch::job_from_desc(const lbib_lattice_desc& d, JobDev& J) {
+    std::memset(&J, 0, sizeof J);
+    J.nx = d.nx; J.ny = d.ny; J.nz = d.nz;
+    J.storage = d.storage;
+    J.n = (long long)d.nx * d.ny * d.nz;
+    J.omega = (float)(1.0 / d.tau);
+    J.guo = (float)(1.0 - 1.0 / (2.0 * d.tau));
+    J.nu = (float)((d.tau - 0.5) / 3.0);
+    J.zh_axis = -1;
+    for (int f = 0; f < 6; ++f) {
+        J.bc[f] = d.bc[f];
+        if (d.bc[f] == 1) J.zh_axis = f / 2;
+        for (int a = 0; a < 3; ++a) J.wall_u[f][a] = (float)d.wall_u[f][a];
+    }
+    for (int a = 0; a < 3; ++a) J.G[a] = (float)d.body_force[a];
+}
+
+lbib_status Batch::create_lattices(const std::vector<lbib_lattice_desc>& descs, int storage_,
+                                   void* stream_, void* ws, size_t ws_bytes,
+                                   const std::vector<char>* skip_init) {
+    stream = (hipStream_t)stream_;
+    storage = storage_;
+    arena.base = ws;
+    arena.cap = ws ? ws_bytes : 0;
+    ldesc = descs;
+    jobs.resize(descs.size());
+    long long off = 0;
+    for (size_t j = 0; j < descs.size(); ++j) {
+        job_from_desc(descs[j], jobs[j]);
+        jobs[j].pop_off = off;
+        off += 19LL * jobs[j].n;
+        jobs[j].body0 = 0;
+        jobs[j].nbodies = 0;
+    }
+    pop_elems = off;
+    lbib_status st = arena.alloc(pop_elems * storage_bytes(storage), &P.popA);
+    if (st) return st;
+    if ((st = arena.alloc(pop_elems * storage_bytes(storage), &P.popB))) return st;
+    void* p;
+    if ((st = arena.alloc(sizeof(int) * jobs.size(), &p))) return st;
+    P.flags = (int*)p;
+    HIP_TRY(hipMemsetAsync(P.flags, 0, sizeof(int) * jobs.size(), stream));
+    if ((st = arena.alloc(sizeof(JobDev) * jobs.size(), &p))) return st;
+    d_jobs = (JobDev*)p;
+    P.jobs = d_jobs;
+    mark_used = arena.used;
+    mark_owned = arena.owned.size();
+    if ((st = retile())) return st;
+    // all jobs at rest
+    for (size_t j = 0; j < jobs.size(); ++j)
+        if (!(skip_init && (*skip_init)[j]))
+            if ((st = init_job((int)j, nullptr, nullptr))) return st;
+    return rebuild_bodies();
+}
+
+// Tile list of the sweep for the current launch shape.
+lbib_status Batch::retile() {
+    tile_job.clear();
+    const long long per = (long long)shape.block * shape.npt;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        jobs[j].tile0 = (int)tile_job.size();
+        jobs[j].ntiles = (int)((jobs[j].n + per - 1) / per);
+        for (int t = 0; t < jobs[j].ntiles; ++t) tile_job.push_back((int)j);
+    }
+    HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, stream));
+    if (d_tile_job && tile_cap < tile_job.size()) {
+        hipStreamSynchronize(stream);
+        hipFree(d_tile_job);
+        d_tile_job = nullptr;
+    }
+    if (!d_tile_job) {
+        tile_cap = std::max<size_t>(tile_job.size(), 1) * 4;
+        HIP_TRY(hipMalloc(&d_tile_job, sizeof(int) * tile_cap));
+    }
+    HIP_TRY(hipMemcpyAsync(d_tile_job, tile_job.data(), sizeof(int) * tile_job.size(), hipMemcpyHostToDevice, stream));
+    P.tile_job = d_tile_job;
+    graph_valid = false;
+    return LBIB_OK;
+}
+
+lbib_status Batch::set_shape(SweepShape s) {
+    shape = s;
+    return retile();
+}
+
+// Re-create every body-related device pool from the host copies (after a body was added).
+lbib_status Batch::rebuild_bodies() {
+    lbib_status st;
+    if ((st = download_body_state())) return st;
+    HIP_TRY(hipStreamSynchronize(stream));
+    arena.release_from(mark_used, mark_owned);
+    // order bodies by job
+    std::stable_sort(hbodies.begin(), hbodies.end(), [](const HostBody& a, const HostBody& b) { return a.job < b.job; });
+    for (auto& J : jobs) { J.body0 = 0; J.nbodies = 0; }
+    std::vector<BodyDev> bd(hbodies.size());
+    std::vector<int> bc, bt, bv;
+    std::vector<double> x, xprev, uv, xb, l0, ks, th0;
+    std::vector<int> tri, edge, hinge, vtp, vtl, vep, vel, vhp, vhl;
+    std::vector<WinDesc> fd(hbodies.size());
+    std::vector<BodyState> bs(hbodies.size());
+    long long v0 = 0, t0 = 0, e0 = 0, woff = 0, red = 0;
+    max_cap = 0;
+    nblk_c = nblk_t = nblk_v = 0;
+    for (size_t i = 0; i < hbodies.size(); ++i) {
+        HostBody& h = hbodies[i];
+        JobDev& J = jobs[h.job];
+        if (J.nbodies == 0) J.body0 = (int)i;
+        J.nbodies++;
+        BodyDev& B = bd[i];
+        std::memset(&B, 0, sizeof B);
+        B.job = h.job; B.rigid = h.desc.rigid; B.integrator = h.desc.integrator;
+        B.nv = h.nv; B.nt = h.nt; B.ne = h.ne;
+        B.v0 = v0; B.t0 = t0; B.e0 = e0;
+        B.vt_off = v0 + (long long)i;  // CSR pointer arrays hold nv+1 entries per body
+        B.ve_off = B.vt_off;
+        B.vh_off = B.vt_off;
+        B.kb = h.desc.kb; B.kv = h.desc.kv; B.mv = h.mv; B.V0 = h.V0; B.mass = h.mass;
+        B.rw = h.desc.mls_rw; B.alpha = h.desc.mls_alpha; B.probe = h.desc.probe_len; B.shell_h = h.desc.shell_h;
+        for (int a = 0; a < 3; ++a) B.gravity[a] = h.desc.gravity[a];
+        for (int k = 0; k < 9; ++k) B.Ib[k] = h.Ib[k];
+        const int dims[3] = {J.nx, J.ny, J.nz};
+        const double grow = h.desc.rigid ? 1.0 : 1.6;
+        for (int a = 0; a < 3; ++a)
+            B.win_cap[a] = std::min(dims[a], (int)std::ceil(2.0 * grow * h.rbound) + 2 * WIN_MARGIN + 4);
+        const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+        B.win_off = woff;
+        woff += capn;
+        max_cap = std::max<long long>(max_cap, capn);
+        const int nbc = (h.nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbv = (h.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
+        B.blk_c0 = nblk_c; B.nblk_c = nbc; nblk_c += nbc;
+        B.blk_t0 = nblk_t; B.nblk_t = nbc; nblk_t += nbc;
+        B.blk_v0 = nblk_v; B.nblk_v = nbv; nblk_v += nbv;
+        for (int k = 0; k < nbc; ++k) { bc.push_back((int)i); bt.push_back((int)i); }
+        for (int k = 0; k < nbv; ++k) bv.push_back((int)i);
+        B.red_slot = (int)red;
+        red += std::max(nbc, nbv);
+        x.insert(x.end(), h.x.begin(), h.x.end());
+        xprev.insert(xprev.end(), h.xprev.begin(), h.xprev.end());
+        uv.insert(uv.end(), h.uv.begin(), h.uv.end());
+        xb.insert(xb.end(), h.xb.begin(), h.xb.end());
+        tri.insert(tri.end(), h.tri.begin(), h.tri.end());
+        edge.insert(edge.end(), h.edge.begin(), h.edge.end());
+        hinge.insert(hinge.end(), h.hinge.begin(), h.hinge.end());
+        l0.insert(l0.end(), h.l0.begin(), h.l0.end());
+        ks.insert(ks.end(), h.ks.begin(), h.ks.end());
+        th0.insert(th0.end(), h.theta0.begin(), h.theta0.end());
+        // CSR pointers are stored relative to this body's list offsets
+        const int ot = (int)vtl.size(), oe = (int)vel.size(), oh = (int)vhl.size();
+        for (int v = 0; v <= h.nv; ++v) {
+            vtp.push_back(ot + h.vt_ptr[v]);
+            vep.push_back(oe + h.ve_ptr[v]);
+            vhp.push_back(oh + h.vh_ptr[v]);
+        }
+        vtl.insert(vtl.end(), h.vt_list.begin(), h.vt_list.end());
+        vel.insert(vel.end(), h.ve_list.begin(), h.ve_list.end());
+        vhl.insert(vhl.end(), h.vh_list.begin(), h.vh_list.end());
+        v0 += h.nv; t0 += h.nt; e0 += h.ne;
+        // state
+        BodyState& S = bs[i];
+        std::memset(&S, 0, sizeof S);
+        if (h.has_state) S = h.state;
+        else {
+            S.V = h.V0;
+            for (int k = 0; k < 9; ++k) S.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+            for (int a = 0; a < 3; ++a) S.X[a] = h.X0[a];
+            double c[3] = {0, 0, 0};
+            for (int v = 0; v < h.nv; ++v) for (int a = 0; a < 3; ++a) c[a] += h.x[3 * v + a];
+            for (int a = 0; a < 3; ++a) S.centre[a] = c[a] / h.nv;
+        }
+        S.counter_c = S.counter_t = S.counter_v = 0;
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int v = 0; v < h.nv; ++v)
+            for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], h.x[3 * v + a]); hi[a] = std::max(hi[a], h.x[3 * v + a]); }
+        bool over = false;
+        fd[i] = h.has_state ? h.fdesc : window_for(J, lo, hi, B.win_cap, &over);
+        if (over) return fail(LBIB_EDOMAIN, "body does not fit its window");
+    }
+    nbodies = (int)hbodies.size();
+    max_red = red;
+    if ((st = upload(arena, bd, (BodyDev**)&P.bodies, stream))) return st;
+    if ((st = upload(arena, bc, (int**)&P.blk_body_c, stream))) return st;
+    if ((st = upload(arena, bt, (int**)&P.blk_body_t, stream))) return st;
+    if ((st = upload(arena, bv, (int**)&P.blk_body_v, stream))) return st;
+    if ((st = upload(arena, x, &P.x, stream))) return st;
+    if ((st = upload(arena, xprev, &P.xprev, stream))) return st;
+    if ((st = upload(arena, uv, &P.uv, stream))) return st;
+    std::vector<double> zero(x.size(), 0.0);
+    if ((st = upload(arena, zero, &P.fv, stream))) return st;
+    for (size_t i = 0; i < hbodies.size(); ++i)
+        if (hbodies[i].has_state && !hbodies[i].fv.empty())
+            HIP_TRY(hipMemcpyAsync(P.fv + 3 * bd[i].v0, hbodies[i].fv.data(), sizeof(double) * hbodies[i].fv.size(), hipMemcpyHostToDevice, stream));
+    if ((st = upload(arena, xb, (double**)&P.xb, stream))) return st;
+    if ((st = upload(arena, tri, (int**)&P.tri, stream))) return st;
+    if ((st = upload(arena, edge, (int**)&P.edge, stream))) return st;
+    if ((st = upload(arena, hinge, (int**)&P.hinge, stream))) return st;
+    if ((st = upload(arena, l0, (double**)&P.l0, stream))) return st;
+    if ((st = upload(arena, ks, (double**)&P.ks, stream))) return st;
+    if ((st = upload(arena, th0, (double**)&P.theta0, stream))) return st;
+    if ((st = upload(arena, vtp, (int**)&P.vt_ptr, stream))) return st;
+    if ((st = upload(arena, vtl, (int**)&P.vt_list, stream))) return st;
+    if ((st = upload(arena, vep, (int**)&P.ve_ptr, stream))) return st;
+    if ((st = upload(arena, vel, (int**)&P.ve_list, stream))) return st;
+    if ((st = upload(arena, vhp, (int**)&P.vh_ptr, stream))) return st;
+    if ((st = upload(arena, vhl, (int**)&P.vh_list, stream))) return st;
+    std::vector<double> fe(3 * (size_t)std::max<long long>(t0, 1), 0.0);
+    if ((st = upload(arena, fe, &P.fext, stream))) return st;
+    void* p;
+    if ((st = arena.alloc(sizeof(long long) * 3 * std::max<long long>(woff, 1), &p))) return st;
+    P.fwin = (long long*)p;
+    HIP_TRY(hipMemsetAsync(P.fwin, 0, sizeof(long long) * 3 * std::max<long long>(woff, 1), stream));
+    if ((st = arena.alloc(sizeof(float4) * std::max<long long>(woff, 1), &p))) return st;
+    P.mwin = (float4*)p;
+    HIP_TRY(hipMemsetAsync(P.mwin, 0, sizeof(float4) * std::max<long long>(woff, 1), stream));
+    if ((st = upload(arena, fd, &P.fdesc, stream))) return st;
+    if ((st = upload(arena, fd, &P.mdesc, stream))) return st;
+    if ((st = upload(arena, bs, &P.bstate, stream))) return st;
+    if ((st = arena.alloc(sizeof(double) * 16 * std::max<long long>(red, 1), &p))) return st;
+    P.partial = (double*)p;
+    d_bodies = (BodyDev*)P.bodies;
+    host_bodies = bd;
+    HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, stream));
+    for (auto& h : hbodies) h.has_state = false;
+    primed = false;
+    graph_valid = false;
+    HIP_TRY(hipStreamSynchronize(stream));
+    return LBIB_OK;
+}
+
+// Copy the dynamic state of existing bodies back to the host copies (before a rebuild).
+lbib_status Batch::download_body_state() {
+    if (nbodies == 0) return LBIB_OK;
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (int i = 0; i < nbodies; ++i) {
+        HostBody& h = hbodies[i];
+        const BodyDev& B = host_bodies[i];
+        HIP_TRY(hipMemcpy(h.x.data(), P.x + 3 * B.v0, sizeof(double) * 3 * h.nv, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(h.xprev.data(), P.xprev + 3 * B.v0, sizeof(double) * 3 * h.nv, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(h.uv.data(), P.uv + 3 * B.v0, sizeof(double) * 3 * h.nv, hipMemcpyDeviceToHost));
+        h.fv.resize(3 * (size_t)h.nv);
+        HIP_TRY(hipMemcpy(h.fv.data(), P.fv + 3 * B.v0, sizeof(double) * 3 * h.nv, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&h.state, P.bstate + i, sizeof(BodyState), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&h.fdesc, P.fdesc + i, sizeof(WinDesc), hipMemcpyDeviceToHost));
+        h.has_state = true;
+    }
+    return LBIB_OK;
+}
+
+lbib_status Batch::add_body(int job, const lbib_body_desc& d, const double* xyz, int nv, const int* tri,
+                            int nt, int* id) {
+    HostBody hb;
+    lbib_status st = build_body(d, xyz, nv, tri, nt, hb);
+    if (st) return st;
+    hb.job = job;
+    if ((st = check_support(jobs[job], hb))) return st;
+    if ((st = download_body_state())) return st;
+    // ids are stable in insertion order per job
+    int local = 0;
+    for (auto& h : hbodies) if (h.job == job) local++;
+    hb.local_id = local;
+    hbodies.push_back(hb);
+    st = rebuild_bodies();
+    if (st) {
+        // drop the body again so the lattice stays usable
+        for (size_t i = 0; i < hbodies.size(); ++i)
+            if (hbodies[i].job == job && hbodies[i].local_id == local) { hbodies.erase(hbodies.begin() + i); break; }
+        return st;
+    }
+    *id = local;
+    return LBIB_OK;
+}
+
+int Batch::body_index(int job, int local) const {
+    for (int i = 0; i < (int)hbodies.size(); ++i)
+        if (hbodies[i].job == job && hbodies[i].local_id == local) return i;
+    return -1;
+}
+
+// ---------------------------------------------------------------- state
+lbib_status Batch::init_job(int job, const double* rho, const double* u) {
+    const long long n = jobs[job].n;
+    double *drho = nullptr, *du = nullptr, *df = nullptr;
+    if (rho) { HIP_TRY(hipMalloc(&drho, sizeof(double) * n)); HIP_TRY(hipMemcpyAsync(drho, rho, sizeof(double) * n, hipMemcpyHostToDevice, stream)); }
+    if (u) { HIP_TRY(hipMalloc(&du, sizeof(double) * 3 * n)); HIP_TRY(hipMemcpyAsync(du, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, stream)); }
+    HIP_TRY(hipMalloc(&df, sizeof(double) * 19 * n));
+    launch_init_eq(job, n, drho, du, df, stream);
+    launch_set_pops(P, storage, cur_b, job, n, df, stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(stream));
+    hipFree(df);
+    if (drho) hipFree(drho);
+    if (du) hipFree(du);
+    primed = false;
+    step_count = 0;
+    return LBIB_OK;
+}
+
+lbib_status Batch::set_populations(int job, const double* f) {
+    const long long n = jobs[job].n;
+    double* df = nullptr;
+    HIP_TRY(hipMalloc(&df, sizeof(double) * 19 * n));
+    HIP_TRY(hipMemcpyAsync(df, f, sizeof(double) * 19 * n, hipMemcpyHostToDevice, stream));
+    launch_set_pops(P, storage, cur_b, job, n, df, stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(stream));
+    hipFree(df);
+    primed = false;
+    return LBIB_OK;
+}
+
+lbib_status Batch::check_flags() {
+    HIP_TRY(hipStreamSynchronize(stream));
+    std::vector<int> fl(jobs.size());
+    HIP_TRY(hipMemcpy(fl.data(), P.flags, sizeof(int) * fl.size(), hipMemcpyDeviceToHost));
+    for (size_t j = 0; j < fl.size(); ++j) {
+        if (fl[j] & FLAG_NONFINITE) return fail(LBIB_EUNSTABLE, "job " + std::to_string(j) + ": non-finite or runaway state");
+        if (fl[j] & FLAG_DOMAIN) return fail(LBIB_EDOMAIN, "job " + std::to_string(j) + ": MLS support or probe reached a wall");
+        if (fl[j] & FLAG_WINDOW) return fail(LBIB_EDOMAIN, "job " + std::to_string(j) + ": body outgrew its window");
+    }
+    return LBIB_OK;
+}
+
+lbib_status Batch::job_flags(std::vector<int>& fl) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    fl.resize(jobs.size());
+    HIP_TRY(hipMemcpy(fl.data(), P.flags, sizeof(int) * fl.size(), hipMemcpyDeviceToHost));
+    return LBIB_OK;
+}
+
+lbib_status Batch::get_macros(int job, double* rho, double* u) {
+    const long long n = jobs[job].n;
+    float* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(float) * 4 * n));
+    launch_macros(P, storage, cur_b, job, n, d, stream);
+    HIP_TRY(hipGetLastError());
+    std::vector<float> h(4 * n);
+    HIP_TRY(hipMemcpyAsync(h.data(), d, sizeof(float) * 4 * n, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    hipFree(d);
+    for (long long k = 0; k < n; ++k) {
+        if (rho) rho[k] = 1.0 + (double)h[4 * k];
+        if (u) for (int a = 0; a < 3; ++a) u[a * n + k] = (double)h[4 * k + 1 + a];
+    }
+    return LBIB_OK;
+}
+
+lbib_status Batch::get_populations(int job, double* f) {
+    const long long n = jobs[job].n;
+    float* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(float) * 19 * n));
+    launch_get_pops(P, storage, cur_b, job, n, d, stream);
+    HIP_TRY(hipGetLastError());
+    std::vector<float> h(19 * n);
+    HIP_TRY(hipMemcpyAsync(h.data(), d, sizeof(float) * 19 * n, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    hipFree(d);
+    for (int i = 0; i < 19; ++i)
+        for (long long k = 0; k < n; ++k) f[i * n + k] = wq(i) + (double)h[i * n + k];
+    return LBIB_OK;
+}
+
+// ---------------------------------------------------------------- stepping
+lbib_status Batch::prime() {
+    launch_window_moments(P, storage, cur_b, nbodies, (int)max_cap, stream);
+    HIP_TRY(hipGetLastError());
+    primed = true;
+    return LBIB_OK;
+}
+
+lbib_status Batch::enqueue_step(bool collide) {
+    const bool bodies = collide && nbodies > 0;
+    if (bodies) launch_centroids(P, nblk_c, stream);
+    if (timing) {
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        HIP_TRY(hipEventRecord(a, stream));
+        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, stream);
+        HIP_TRY(hipEventRecord(b, stream));
+        sweep_events.push_back({a, b});
+    } else {
+        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, stream);
+    }
+    cur_b = !cur_b;
+    if (bodies) {
+        launch_window_moments(P, storage, cur_b, nbodies, (int)max_cap, stream);
+        launch_triangles(P, nblk_t, stream);
+        launch_vertices(P, nblk_v, stream);
+    }
+    HIP_TRY(hipGetLastError());
+    return LBIB_OK;
+}
+
+lbib_status Batch::step(int nsteps, bool collide) {
+    if (nsteps < 0) return fail(LBIB_EINVAL, "negative step count");
+    lbib_status st;
+    if (collide && nbodies > 0 && !primed)
+        if ((st = prime())) return st;
+    if (!collide) primed = false;
+    if (use_graph && collide && !timing) {
+        // a graph holds two steps (A->B, B->A) so the buffer parity returns to the start
+        int k = 0;
+        if (cur_b && nsteps > 0) { if ((st = enqueue_step(true))) return st; k = 1; ++step_count; }
+        const int pairs = (nsteps - k) / 2;
+        if (pairs > 0) {
+            if (!graph_valid) { if ((st = capture_graph())) return st; }
+            for (int p = 0; p < pairs; ++p) HIP_TRY(hipGraphLaunch(graph_exec, stream));
+            step_count += 2LL * pairs;
+        }
+        if ((nsteps - k) % 2) { if ((st = enqueue_step(true))) return st; ++step_count; }
+        return LBIB_OK;
+    }
+    hipEvent_t s0 = nullptr, s1 = nullptr;
+    if (timing) {
+        HIP_TRY(hipEventCreate(&s0));
+        HIP_TRY(hipEventCreate(&s1));
+        HIP_TRY(hipEventRecord(s0, stream));
+    }
+    for (int i = 0; i < nsteps; ++i) {
+        if ((st = enqueue_step(collide))) return st;
+        ++step_count;
+    }
+    if (timing) {
+        HIP_TRY(hipEventRecord(s1, stream));
+        step_events.push_back({s0, s1});
+        step_event_steps += nsteps;
+    }
+    return LBIB_OK;
+}
+
+lbib_status Batch::capture_graph() {
+    if (graph_exec) { hipGraphExecDestroy(graph_exec); graph_exec = nullptr; }
+    if (graph) { hipGraphDestroy(graph); graph = nullptr; }
+    if (!capture_stream) HIP_TRY(hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking));
+    hipStream_t user = stream;
+    HIP_TRY(hipStreamSynchronize(user));
+    stream = capture_stream;
+    const bool start_b = cur_b;
+    HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    lbib_status st = enqueue_step(true);
+    if (!st) st = enqueue_step(true);
+    hipError_t e = hipStreamEndCapture(stream, &graph);
+    stream = user;
+    cur_b = start_b;
+    if (st) return st;
+    if (e != hipSuccess) return fail(LBIB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    HIP_TRY(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+    graph_valid = true;
+    return LBIB_OK;
+}
+
+lbib_status Batch::kernel_time(int kernel, double* ms, int64_t* count) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    double total = 0.0;
+    int64_t c = 0;
+    auto& ev = kernel == 0 ? sweep_events : step_events;
+    for (auto& pr : ev) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second));
+        total += t;
+        ++c;
+    }
+    if (kernel == 1) c = step_event_steps;
+    *ms = total;
+    *count = c;
+    return LBIB_OK;
+}
+
+void Batch::clear_events() {
+    for (auto& pr : sweep_events) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
+    for (auto& pr : step_events) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
+    sweep_events.clear();
+    step_events.clear();
+    step_event_steps = 0;
+}
+
+Batch::~Batch() {
+    if (stream) hipStreamSynchronize(stream);
+    clear_events();
+    if (graph_exec) hipGraphExecDestroy(graph_exec);
+    if (graph) hipGraphDestroy(graph);
+    if (capture_stream) hipStreamDestroy(capture_stream);
+    if (d_tile_job) hipFree(d_tile_job);
+}
+
+// ---------------------------------------------------------------- body state access
+lbib_status Batch::body_state(int bi, double* xyz, double* vel) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    const BodyDev& B = host_bodies[bi];
+    if (xyz) HIP_TRY(hipMemcpy(xyz, P.x + 3 * B.v0, sizeof(double) * 3 * B.nv, hipMemcpyDeviceToHost));
+    if (vel) HIP_TRY(hipMemcpy(vel, P.uv + 3 * B.v0, sizeof(double) * 3 * B.nv, hipMemcpyDeviceToHost));
+    return LBIB_OK;
+}
+
+lbib_status Batch::body_forces(int bi, double* fv, double* F, double* M) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    const BodyDev& B = host_bodies[bi];
+    if (fv) HIP_TRY(hipMemcpy(fv, P.fv + 3 * B.v0, sizeof(double) * 3 * B.nv, hipMemcpyDeviceToHost));
+    BodyState S;
+    HIP_TRY(hipMemcpy(&S, P.bstate + bi, sizeof S, hipMemcpyDeviceToHost));
+    if (F) for (int a = 0; a < 3; ++a) F[a] = S.F[a];
+    if (M) for (int a = 0; a < 3; ++a) M[a] = S.M[a];
+    return LBIB_OK;
+}
+
+lbib_status Batch::body_set_velocity(int bi, const double* v) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    const BodyDev& B = host_bodies[bi];
+    std::vector<double> x(3 * (size_t)B.nv), uv(3 * (size_t)B.nv), xp(3 * (size_t)B.nv);
+    HIP_TRY(hipMemcpy(x.data(), P.x + 3 * B.v0, sizeof(double) * x.size(), hipMemcpyDeviceToHost));
+    if (!B.rigid) {
+        for (size_t i = 0; i < x.size(); ++i) { uv[i] = v[i]; xp[i] = x[i] - v[i]; }
+    } else {
+        BodyState S;
+        HIP_TRY(hipMemcpy(&S, P.bstate + bi, sizeof S, hipMemcpyDeviceToHost));
+        for (int a = 0; a < 3; ++a) { S.u[a] = S.u1[a] = v[a]; S.om[a] = S.om1[a] = v[3 + a]; }
+        HIP_TRY(hipMemcpy(P.bstate + bi, &S, sizeof S, hipMemcpyHostToDevice));
+        for (int k = 0; k < B.nv; ++k) {
+            double r[3] = {x[3 * k] - S.X[0], x[3 * k + 1] - S.X[1], x[3 * k + 2] - S.X[2]}, w[3];
+            vcross(S.om, r, w);
+            for (int a = 0; a < 3; ++a) { uv[3 * k + a] = S.u[a] + w[a]; xp[3 * k + a] = x[3 * k + a]; }
+        }
+    }
+    HIP_TRY(hipMemcpy(P.uv + 3 * B.v0, uv.data(), sizeof(double) * uv.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(P.xprev + 3 * B.v0, xp.data(), sizeof(double) * xp.size(), hipMemcpyHostToDevice));
+    return LBIB_OK;
+}
+
+size_t Batch::device_bytes() const {
+    return arena.base ? arena.used : arena.total;
+}
+
+}  // namespace lbib

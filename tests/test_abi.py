@@ -1,0 +1,63 @@
+"""The C-ABI library loads without a GPU and exports every entry point include/lbib.h
+declares (no compute calls).  Also checks the binding's struct layouts against the header."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbib.h")
+SO = os.path.join(ROOT, "paper_2207_06029_amd", "liblbib.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbib_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(SO):
+        pytest.fail("liblbib.so has not been built (run __graft_entry__.build())")
+    return ctypes.CDLL(SO)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2207_06029_amd import _lib
+    assert sorted(_lib.SIGNATURES) == declared_functions()
+
+
+def test_abi_version_and_struct_sizes(lib):
+    from paper_2207_06029_amd import _lib
+    lib.lbib_abi_version.restype = ctypes.c_uint32
+    assert lib.lbib_abi_version() == 1
+    # sizes that follow from the C declarations (natural alignment, 8-byte doubles)
+    assert ctypes.sizeof(_lib.lbib_lattice_desc) == 4 * 4 + 8 + 6 * 4 + 18 * 8 + 3 * 8
+    assert ctypes.sizeof(_lib.lbib_body_desc) == 2 * 4 + 5 * 8 + 3 * 8 + 4 * 8
+
+
+def test_descriptor_validation_without_gpu(lib):
+    """Host-side validation runs before any device call."""
+    from paper_2207_06029_amd import _lib, api
+    from paper_2207_06029_amd import inputs as I
+    L = _lib.load()
+    spec = I.LatticeSpec(8, 8, 8, 0.4)          # tau <= 1/2
+    d = api.lattice_desc(spec)
+    out = ctypes.c_size_t()
+    assert L.lbib_workspace_bytes(ctypes.byref(d), 0, 0, ctypes.byref(out)) == -1
+    spec = I.LatticeSpec(8, 8, 8, 0.8, bc=(0, 1, 0, 0, 0, 0))  # periodic face without partner
+    d = api.lattice_desc(spec)
+    assert L.lbib_workspace_bytes(ctypes.byref(d), 0, 0, ctypes.byref(out)) == -1
+    spec = I.LatticeSpec(8, 8, 8, 0.8)
+    d = api.lattice_desc(spec)
+    assert L.lbib_workspace_bytes(ctypes.byref(d), 0, 0, ctypes.byref(out)) == 0
+    assert out.value >= 2 * 19 * 512 * 4

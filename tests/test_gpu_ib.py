@@ -1,0 +1,137 @@
+"""GPU parity of the immersed-boundary coupling and structure updates (Secs. 1.2-1.3) against the
+FP64 oracle, through the C ABI."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2207_06029_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2207_06029_amd import api as A
+    return A
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _threads(orc):
+    orc.set_threads(max(1, min(16, os.cpu_count() or 1)))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_pair(api, orc, job, steps, chunks=1, vel=None):
+    lat = api.Lattice(job.lattice)
+    b = lat.add_body(job.body, job.xyz, job.tri)
+    ref = orc.Lattice(job.lattice)
+    rb = ref.add_body(job.body, job.xyz, job.tri)
+    if vel is not None:
+        lat.set_velocity(b, vel)
+        ref.set_velocity(rb, vel)
+    for _ in range(chunks):
+        lat.step(steps // chunks)
+        ref.step(steps // chunks)
+    lat.sync()
+    return lat, b, ref, rb
+
+
+def compare(lat, b, ref, rb, tol_u, tol_x, label=""):
+    _, u = lat.macros()
+    _, ur = ref.macros()
+    x, v = lat.body_state(b)
+    xr, vr = ref.body_state(rb)
+    x0 = None
+    eu, ex = rel_l2(u, ur), rel_l2(x, xr)
+    print(f"{label}: rel-L2 u* {eu:.3e}  positions {ex:.3e}  vertex velocity {rel_l2(v, vr):.3e}")
+    assert eu < tol_u
+    assert ex < tol_x
+    return eu, ex
+
+
+def test_capsule_shear_small_1000_steps(api, orc):
+    """Full 32^3 capsule-in-shear case over 1000 steps: rel-L2 <= 1e-5 on u* and positions."""
+    job = I.capsule_shear_small()
+    lat, b, ref, rb = run_pair(api, orc, job, 1000, chunks=4)
+    compare(lat, b, ref, rb, 1e-5, 1e-5, "capsule_shear_32")
+    x, _ = lat.body_state(b)
+    xr, _ = ref.body_state(rb)
+    disp = rel_l2(x - job.xyz, xr - job.xyz)
+    print(f"displacement rel-L2 {disp:.3e}")
+    fv, F, M = lat.body_forces(b)
+    fvr, Fr, Mr = ref.body_forces(rb)
+    assert rel_l2(fv, fvr) < 1e-4
+
+
+def test_capsule_paper_integrator_short(api, orc):
+    job = I.capsule_shear_small()
+    job.body.integrator = I.INTEGRATOR_PAPER
+    lat, b, ref, rb = run_pair(api, orc, job, 120)
+    compare(lat, b, ref, rb, 1e-5, 1e-5, "paper integrator")
+
+
+def test_capsule_volume_penalty_and_bending(api, orc):
+    # k_v = 1: the explicit breathing mode has omega^2 = 3 k_v / (R rho_s T) = 0.5 (stable)
+    job = I.capsule_shear_small()
+    job.body.kv = 1.0
+    job.body.kb = 0.005
+    lat, b, ref, rb = run_pair(api, orc, job, 300)
+    compare(lat, b, ref, rb, 1e-5, 1e-5, "kv=10")
+
+
+def test_rigid_settling_small(api, orc):
+    lat_spec = I.LatticeSpec(32, 32, 64, 0.7, **I.closed_box())
+    xyz, tri = I.spheroid_mesh(3, (4.0, 4.0, 4.0), (15.5, 15.5, 48.0))
+    body = I.BodySpec(rigid=1, ks0=0.0, kb=0.0, kv=0.0, mass_ratio=2.0, gravity=(0.0, 0.0, -1e-4))
+    job = I.Job("settle", lat_spec, body, xyz, tri, 400)
+    lat, b, ref, rb = run_pair(api, orc, job, 400, chunks=2)
+    compare(lat, b, ref, rb, 1e-5, 1e-6, "rigid settling")
+    _, F, M = lat.body_forces(b)
+    _, Fr, Mr = ref.body_forces(rb)
+    assert rel_l2(F, Fr) < 1e-4
+
+
+def test_rigid_rotating_spheroid_in_shear(api, orc):
+    spec = I.LatticeSpec(40, 33, 32, 0.8, **I.shear_walls(0.01))
+    rot = I.uniform_rotation(np.random.default_rng(3))
+    xyz, tri = I.spheroid_mesh(3, (8.0, 4.0, 4.0), (19.5, 16.0, 15.5), rot)
+    body = I.BodySpec(rigid=1, ks0=0.0, kb=0.0, kv=0.0, mass_ratio=1.0)
+    job = I.Job("jeffery_small", spec, body, xyz, tri, 300)
+    lat, b, ref, rb = run_pair(api, orc, job, 300)
+    compare(lat, b, ref, rb, 1e-5, 1e-6, "rigid spheroid")
+
+
+def test_galilean_translation_gpu(api):
+    n = 20
+    U0 = np.array([0.01, -0.004, 0.007])
+    spec = I.LatticeSpec(n, n, n, 0.8)
+    lat = api.Lattice(spec)
+    lat.init(np.ones(n ** 3), np.repeat(U0[:, None], n ** 3, axis=1))
+    xyz, tri = I.spheroid_mesh(2, (4.0, 3.0, 3.0), (9.5, 9.5, 9.5),
+                               I.uniform_rotation(np.random.default_rng(5)))
+    b = lat.add_body(I.BodySpec(rigid=0, ks0=0.01, kb=0.001, kv=1.0, mass_ratio=1.3), xyz, tri)
+    lat.set_velocity(b, np.repeat(U0[None, :], len(xyz), axis=0))
+    lat.step(40)
+    x, v = lat.body_state(b)
+    np.testing.assert_allclose(x, xyz + 40 * U0, rtol=0, atol=2e-6)
+    _, u = lat.macros()
+    np.testing.assert_allclose(u, np.repeat(U0[:, None], n ** 3, axis=1), atol=1e-6)
+
+
+def test_two_bodies_in_one_lattice(api, orc):
+    spec = I.LatticeSpec(40, 32, 24, 0.8, **I.shear_walls(0.01))
+    body = I.BodySpec(rigid=0, ks0=0.01, kb=0.001, kv=0.0, mass_ratio=1.0)
+    m1 = I.spheroid_mesh(2, (4.0, 4.0, 4.0), (11.0, 15.5, 11.5))
+    m2 = I.spheroid_mesh(2, (3.0, 4.0, 3.0), (27.0, 16.5, 12.0))
+    lat = api.Lattice(spec)
+    ref = orc.Lattice(spec)
+    ids = [lat.add_body(body, *m1), lat.add_body(body, *m2)]
+    rids = [ref.add_body(body, *m1), ref.add_body(body, *m2)]
+    lat.step(200)
+    ref.step(200)
+    for i, r in zip(ids, rids):
+        compare(lat, i, ref, r, 1e-5, 1e-6, f"body {i}")
