@@ -7,14 +7,17 @@
 // no lane waits on another except for the butterfly sums.
 //
 // Step order inside the time step n -> n+1:
-//   k_centroids  geometry at x^n, MLS at centroids on moments of f^n, F_l = U_b - U*,
-//                fixed-point spreading into the body's force window, enclosed volume V^n
+//   k_centroids  triangle blocks: force window of this step from the vertex bounding box,
+//                geometry at x^n, MLS at centroids on moments of f^n, F_l = U_b - U*, fixed-point
+//                spreading into the body's force window, enclosed volume V^n (k_v != 0);
+//                edge blocks: spring and bending forces of every hinge at x^n
 //   (sweep)      collide+stream with the spread force
 //   (moments)    moments of f^{n+1} in the body's window
-//   k_triangles  probe stresses on f^{n+1} (Eqs. hydroForP, hydroForNu); rigid bodies: FP64
-//                totals and the velocity / pose update in the last block
-//   k_vertices   vertex velocity from the fluid, internal forces at x^n, membrane update;
-//                bounding box of x^{n+1} -> force window of the next step
+//   k_triangles  one group per probe: stresses on f^{n+1} (Eqs. hydroForP, hydroForNu), volume
+//                force per triangle; rigid bodies: FP64 totals and the velocity / pose update
+//                in the last block
+//   k_vertices   vertex velocity from the fluid, gathered forces, membrane update, integer
+//                bounding box of x^{n+1} for the next step's window
 #include "lbib_internal.h"
 
 namespace lbib {
@@ -124,34 +127,148 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-// Deterministic per-body block reduction: thread 0 of each block stores nval partials, the
-// last block to arrive sums them in block order.  Returns true in thread 0 of the last block,
-// with the totals in out[].
-__device__ bool last_block_sum(const Pools& P, const BodyDev& B, int blk, int nblk, int* counter,
-                               const double* mine, int nval, double* out) {
-    double* slot = P.partial + 16LL * (B.red_slot + blk);
-    for (int i = 0; i < nval; ++i) slot[i] = mine[i];
+// Deterministic per-body reduction across the blocks of one body.  Thread 0 of every block
+// publishes nval partials (op[i] = 0 sum, 1 min, 2 max); the last block to arrive folds them
+// with all its threads: thread t takes blocks t, t+256, ... in order, then a fixed-shape tree
+// in LDS combines the 256 results.  The order depends only on the body's own block count, so
+// totals are bitwise reproducible and independent of other jobs in the launch.  Returns true
+// in every thread of the last block; out[] is valid in all its threads.
+constexpr int RED_MAX = 9;
+
+__device__ bool last_block_reduce(const Pools& P, const BodyDev& B, int blk, int nblk, int* counter,
+                                  const double* mine, const int* op, int nval, double* out) {
+    __shared__ int s_last;
+    __shared__ double s_red[RED_MAX][256];
+    if (threadIdx.x == 0) {
+        double* slot = P.partial + 16LL * (B.red_slot + blk);
+        for (int i = 0; i < nval; ++i) slot[i] = mine[i];
+        __threadfence();
+        s_last = atomicAdd(counter, 1) == nblk - 1;
+    }
+    __syncthreads();
+    if (!s_last) return false;
     __threadfence();
-    const int done = atomicAdd(counter, 1);
-    if (done != nblk - 1) return false;
-    __threadfence();
-    for (int i = 0; i < nval; ++i) out[i] = 0.0;
-    for (int k = 0; k < nblk; ++k)
-        for (int i = 0; i < nval; ++i) out[i] += agent_load(P.partial + 16LL * (B.red_slot + k) + i);
-    *counter = 0;
+    const int t = threadIdx.x;
+    for (int i = 0; i < nval; ++i) {
+        double acc = op[i] == 0 ? 0.0 : (op[i] == 1 ? 1e300 : -1e300);
+        for (int k = t; k < nblk; k += 256) {
+            const double v = agent_load(P.partial + 16LL * (B.red_slot + k) + i);
+            acc = op[i] == 0 ? acc + v : (op[i] == 1 ? fmin(acc, v) : fmax(acc, v));
+        }
+        s_red[i][t] = acc;
+    }
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w)
+            for (int i = 0; i < nval; ++i) {
+                const double a = s_red[i][t], b = s_red[i][t + w];
+                s_red[i][t] = op[i] == 0 ? a + b : (op[i] == 1 ? fmin(a, b) : fmax(a, b));
+            }
+        __syncthreads();
+    }
+    for (int i = 0; i < nval; ++i) out[i] = s_red[i][0];
+    if (t == 0) *counter = 0;
     return true;
 }
 
-// ---------------------------------------------------------------- centroids
-__global__ void __launch_bounds__(256) k_centroids(Pools P) {
+// ---------------------------------------------------------------- window of a step
+// Force window = integer bounding box of the vertices plus WIN_MARGIN on each side, wrapped on
+// periodic axes, clipped on walled axes, never larger than the reserved capacity.
+__device__ __forceinline__ WinDesc window_from_box(const JobDev& J, const BodyDev& B, const int* bmin,
+                                                   const int* bmax, int& flag) {
+    WinDesc d;
+    const int dims[3] = {J.nx, J.ny, J.nz};
+    for (int a = 0; a < 3; ++a) {
+        int l = bmin[a] - WIN_MARGIN, h = bmax[a] + WIN_MARGIN;
+        if (h < l) { flag |= FLAG_NONFINITE; l = 0; h = 0; }
+        if (J.bc[2 * a] == 0) {
+            const int w = h - l + 1;
+            if (w >= dims[a]) { d.o[a] = 0; d.w[a] = dims[a]; }
+            else { int o = l % dims[a]; if (o < 0) o += dims[a]; d.o[a] = o; d.w[a] = w; }
+        } else {
+            if (l < 0) l = 0;
+            if (h > dims[a] - 1) h = dims[a] - 1;
+            d.o[a] = l < dims[a] ? l : dims[a] - 1;
+            d.w[a] = h >= l ? h - l + 1 : 1;
+        }
+        if (d.w[a] > B.win_cap[a]) { flag |= FLAG_WINDOW; d.w[a] = B.win_cap[a]; }
+        if (d.w[a] < 1) d.w[a] = 1;
+    }
+    return d;
+}
+
+// ---------------------------------------------------------------- hinge forces
+// Spring (Eq. strainFor) on the edge x1-x2 and bending -k_b sin(theta - theta0) dtheta/dx_r on
+// the four hinge vertices, theta the signed angle between the outward normals of (x1,x2,x3)
+// and (x2,x1,x4) about x1->x2.  out[0..2] = spring force on x1 (x2 gets the opposite),
+// out[3+3r..] = bending force on vertex r.
+__device__ void hinge_forces(const Pools& P, const BodyDev& B, int e, double out[15]) {
+    const int* hv = P.hinge + 4 * (B.e0 + e);
+    double x1[3], x2[3], x3[3], x4[3];
+    load3(P.x + 3 * (B.v0 + hv[0]), x1);
+    load3(P.x + 3 * (B.v0 + hv[1]), x2);
+    load3(P.x + 3 * (B.v0 + hv[2]), x3);
+    load3(P.x + 3 * (B.v0 + hv[3]), x4);
+    double e12[3], p3[3], p4[3], q[3];
+    for (int a = 0; a < 3; ++a) { e12[a] = x2[a] - x1[a]; p3[a] = x3[a] - x1[a]; p4[a] = x4[a] - x2[a]; q[a] = -e12[a]; }
+    const double le2 = dot3(e12, e12), le = sqrt(le2);
+    const double sp = -P.ks[B.e0 + e] * (le - P.l0[B.e0 + e]) / le;
+    for (int a = 0; a < 3; ++a) out[a] = -sp * e12[a];   // r_12 = x1 - x2 = -e12
+    if (B.kb == 0.0) {
+        for (int i = 3; i < 15; ++i) out[i] = 0.0;
+        return;
+    }
+    double N1[3], N2[3], c12[3];
+    cross3(e12, p3, N1);
+    cross3(q, p4, N2);
+    const double a1 = sqrt(dot3(N1, N1)), a2 = sqrt(dot3(N2, N2));
+    const double n1[3] = {N1[0] / a1, N1[1] / a1, N1[2] / a1};
+    const double n2[3] = {N2[0] / a2, N2[1] / a2, N2[2] / a2};
+    cross3(n1, n2, c12);
+    const double theta = atan2(dot3(c12, e12) / le, dot3(n1, n2));
+    // opposite vertices rotate their triangle about the edge with lever arm = height over it;
+    // the edge vertices carry the reaction split at each opposite vertex's foot point
+    const double h3 = a1 / le, h4 = a2 / le;
+    const double d4[3] = {x4[0] - x1[0], x4[1] - x1[1], x4[2] - x1[2]};
+    const double t3 = dot3(p3, e12) / le2, t4 = dot3(d4, e12) / le2;
+    const double sb = -B.kb * sin(theta - P.theta0[B.e0 + e]);
+    for (int a = 0; a < 3; ++a) {
+        const double g3 = -n1[a] / h3, g4 = -n2[a] / h4;
+        out[3 + a] = sb * ((t3 - 1.0) * g3 + (t4 - 1.0) * g4);
+        out[6 + a] = sb * (-t3 * g3 - t4 * g4);
+        out[9 + a] = sb * g3;
+        out[12 + a] = sb * g4;
+    }
+}
+
+// ---------------------------------------------------------------- centroids (+ hinges)
+__global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri) {
+    if ((int)blockIdx.x >= nblk_tri) {
+        // edge blocks: one thread per hinge of a membrane
+        const int eb = blockIdx.x - nblk_tri;
+        const int b = P.blk_body_e[eb];
+        const BodyDev& B = P.bodies[b];
+        const int e = (eb - B.blk_e0) * 256 + threadIdx.x;
+        if (e >= B.ne) return;
+        double f[15];
+        hinge_forces(P, B, e, f);
+        double* o = P.fedge + 15LL * (B.e0 + e);
+        for (int i = 0; i < 15; ++i) o[i] = f[i];
+        return;
+    }
     const int b = P.blk_body_c[blockIdx.x];
     const BodyDev& B = P.bodies[b];
     const JobDev& J = P.jobs[B.job];
+    BodyState& S = P.bstate[b];
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_c0;
     const int t = blk * MLS_PER_BLOCK + grp;
     __shared__ double vol[MLS_PER_BLOCK];
     int err = 0;
+    // this step's force window (every block derives the same descriptor; block 0 publishes it)
+    const int bmin[3] = {S.bmin[0], S.bmin[1], S.bmin[2]}, bmax[3] = {S.bmax[0], S.bmax[1], S.bmax[2]};
+    const WinDesc fd = window_from_box(J, B, bmin, bmax, err);
+    if (blk == 0 && threadIdx.x == 0) P.fdesc[b] = fd;
     double Vt = 0.0;
     if (t < B.nt) {
         const int* tv = P.tri + 3 * (B.t0 + t);
@@ -159,6 +276,12 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P) {
         load3(P.x + 3 * (B.v0 + tv[0]), xa);
         load3(P.x + 3 * (B.v0 + tv[1]), xb_);
         load3(P.x + 3 * (B.v0 + tv[2]), xc);
+        double Ub[3];
+        if (!B.rigid) {
+            for (int a = 0; a < 3; ++a)
+                Ub[a] = (P.uv[3 * (B.v0 + tv[0]) + a] + P.uv[3 * (B.v0 + tv[1]) + a] +
+                         P.uv[3 * (B.v0 + tv[2]) + a]) * (1.0 / 3.0);
+        }
         double cen[3], ab[3], ac[3], N[3];
         for (int a = 0; a < 3; ++a) {
             cen[a] = (xa[a] + xb_[a] + xc[a]) * (1.0 / 3.0);
@@ -167,19 +290,19 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P) {
         }
         cross3(ab, ac, N);
         const double A = 0.5 * sqrt(dot3(N, N));
-        // signed volume of the tetrahedron (r, a, b, c), r = vertex 0 of the body
-        double r0[3], pa[3], pb[3], pc[3], bc[3];
-        load3(P.x + 3 * B.v0, r0);
-        for (int a = 0; a < 3; ++a) { pa[a] = xa[a] - r0[a]; pb[a] = xb_[a] - r0[a]; pc[a] = xc[a] - r0[a]; }
-        cross3(pb, pc, bc);
-        Vt = dot3(pa, bc) * (1.0 / 6.0);
-
+        if (!B.rigid && B.kv != 0.0) {
+            // signed volume of the tetrahedron (r, a, b, c), r = vertex 0 of the body
+            double r0[3], pa[3], pb[3], pc[3], bc[3];
+            load3(P.x + 3 * B.v0, r0);
+            for (int a = 0; a < 3; ++a) { pa[a] = xa[a] - r0[a]; pb[a] = xb_[a] - r0[a]; pc[a] = xc[a] - r0[a]; }
+            cross3(pb, pc, bc);
+            Vt = dot3(pa, bc) * (1.0 / 6.0);
+        }
         MlsLane m;
         mls_point(J, cen, B.rw, B.alpha, lane, false, m, err);
         float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
         if (m.active) {
-            const WinDesc md = P.mdesc[b];
-            const long long l = win_index(J, md, m.gx, m.gy, m.gz);
+            const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
             if (l < 0) err |= FLAG_WINDOW;
             else mom = P.mwin[B.win_off + l];
         }
@@ -187,67 +310,61 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P) {
         const double U1 = gsum(m.phi * (double)mom.z);
         const double U2 = gsum(m.phi * (double)mom.w);
         // desired boundary velocity U_b (Sec. 1.2)
-        double Ub[3];
-        if (!B.rigid) {
-            for (int a = 0; a < 3; ++a)
-                Ub[a] = (P.uv[3 * (B.v0 + tv[0]) + a] + P.uv[3 * (B.v0 + tv[1]) + a] +
-                         P.uv[3 * (B.v0 + tv[2]) + a]) * (1.0 / 3.0);
-        } else {
-            const BodyState& S = P.bstate[b];
+        if (B.rigid) {
             double rr[3] = {cen[0] - S.X[0], cen[1] - S.X[1], cen[2] - S.X[2]}, w[3];
             cross3(S.om, rr, w);
             for (int a = 0; a < 3; ++a) Ub[a] = S.u[a] + w[a];
         }
         // F_l = (U_b - U*) / dt, spread with c_l = A_l h (Eq. bodyforce)
-        const double cl = A * B.shell_h;
         if (m.active) {
-            const double s = cl * m.phi;
-            const WinDesc fd = P.fdesc[b];
+            const double sc = A * B.shell_h * m.phi;
             const long long l = win_index(J, fd, m.gx, m.gy, m.gz);
             if (l < 0) {
                 err |= FLAG_WINDOW;
             } else {
                 const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
                 unsigned long long* fw = (unsigned long long*)(P.fwin + 3 * B.win_off + l);
-                const long long q0 = __double2ll_rn(s * (Ub[0] - U0) * FIX_SCALE);
-                const long long q1 = __double2ll_rn(s * (Ub[1] - U1) * FIX_SCALE);
-                const long long q2 = __double2ll_rn(s * (Ub[2] - U2) * FIX_SCALE);
-                atomicAdd(fw, (unsigned long long)q0);
-                atomicAdd(fw + capn, (unsigned long long)q1);
-                atomicAdd(fw + 2 * capn, (unsigned long long)q2);
+                atomicAdd(fw, (unsigned long long)__double2ll_rn(sc * (Ub[0] - U0) * FIX_SCALE));
+                atomicAdd(fw + capn, (unsigned long long)__double2ll_rn(sc * (Ub[1] - U1) * FIX_SCALE));
+                atomicAdd(fw + 2 * capn, (unsigned long long)__double2ll_rn(sc * (Ub[2] - U2) * FIX_SCALE));
             }
         }
     }
-    if (lane == 0) vol[grp] = Vt;
     if (err) atomicOr(P.flags + B.job, err);
+    if (B.rigid || B.kv == 0.0) return;
+    if (lane == 0) vol[grp] = Vt;
     __syncthreads();
-    if (threadIdx.x == 0 && !B.rigid) {
-        double s = 0.0;
-        for (int g = 0; g < MLS_PER_BLOCK; ++g) s += vol[g];
-        double V;
-        if (last_block_sum(P, B, blk, B.nblk_c, &P.bstate[b].counter_c, &s, 1, &V)) P.bstate[b].V = V;
-    }
+    double sv = 0.0;
+    for (int g = 0; g < MLS_PER_BLOCK; ++g) sv += vol[g];
+    const int op[1] = {0};
+    double V;
+    if (last_block_reduce(P, B, blk, B.nblk_c, &S.counter_c, &sv, op, 1, &V) && threadIdx.x == 0) S.V = V;
 }
 
 // ---------------------------------------------------------------- triangles (probes)
+// Group 2k evaluates the outer probe of triangle k of the block, group 2k+1 the inner one.
 __global__ void __launch_bounds__(256) k_triangles(Pools P) {
     const int b = P.blk_body_t[blockIdx.x];
     const BodyDev& B = P.bodies[b];
     const JobDev& J = P.jobs[B.job];
+    BodyState& S = P.bstate[b];
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_t0;
-    const int t = blk * MLS_PER_BLOCK + grp;
-    __shared__ double red[MLS_PER_BLOCK][6];
+    const int k = grp >> 1, side = grp & 1;
+    const int t = blk * TRI_PER_BLOCK + k;
+    __shared__ double probe[MLS_PER_BLOCK][10];
+    __shared__ double red[TRI_PER_BLOCK][6];
+    // the bounding-box accumulators were consumed by k_centroids; restart them for k_vertices
+    if (blk == 0 && threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) { S.bmin[a] = 0x7fffffff; S.bmax[a] = -0x7fffffff; }
     int err = 0;
-    double Ft[3] = {0.0, 0.0, 0.0}, Mt[3] = {0.0, 0.0, 0.0};
-    BodyState& S = P.bstate[b];
+    double cen[3] = {0, 0, 0}, N[3] = {0, 0, 0}, nrm[3] = {0, 0, 0}, A = 0.0;
     if (t < B.nt) {
         const int* tv = P.tri + 3 * (B.t0 + t);
-        double xa[3], xb_[3], xc[3];
+        double xa[3], xb_[3], xc[3], ab[3], ac[3];
         load3(P.x + 3 * (B.v0 + tv[0]), xa);
         load3(P.x + 3 * (B.v0 + tv[1]), xb_);
         load3(P.x + 3 * (B.v0 + tv[2]), xc);
-        double cen[3], ab[3], ac[3], N[3];
         for (int a = 0; a < 3; ++a) {
             cen[a] = (xa[a] + xb_[a] + xc[a]) * (1.0 / 3.0);
             ab[a] = xb_[a] - xa[a];
@@ -255,57 +372,65 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
         }
         cross3(ab, ac, N);
         const double ln = sqrt(dot3(N, N));
-        const double A = 0.5 * ln;
-        const double nrm[3] = {N[0] / ln, N[1] / ln, N[2] / ln};
-        const WinDesc md = P.mdesc[b];
-        double drho_s[2], gu[2][3][3];
-        for (int side = 0; side < 2; ++side) {
-            const double sg = side == 0 ? 1.0 : -1.0;
-            const double xp[3] = {cen[0] + sg * B.probe * nrm[0], cen[1] + sg * B.probe * nrm[1],
-                                  cen[2] + sg * B.probe * nrm[2]};
-            MlsLane m;
-            mls_point(J, xp, B.rw, B.alpha, lane, true, m, err);
-            float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (m.active) {
-                const long long l = win_index(J, md, m.gx, m.gy, m.gz);
-                if (l < 0) err |= FLAG_WINDOW;
-                else mom = P.mwin[B.win_off + l];
-            } else {
-                m.gr[0] = m.gr[1] = m.gr[2] = 0.0;
-            }
-            drho_s[side] = gsum(m.phi * (double)mom.x);
-            const double uc[3] = {mom.y, mom.z, mom.w};
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) gu[side][i][j] = gsum(m.gr[j] * uc[i]);
+        A = 0.5 * ln;
+        for (int a = 0; a < 3; ++a) nrm[a] = N[a] / ln;
+        const double sg = side == 0 ? 1.0 : -1.0;
+        const double xp[3] = {cen[0] + sg * B.probe * nrm[0], cen[1] + sg * B.probe * nrm[1],
+                              cen[2] + sg * B.probe * nrm[2]};
+        MlsLane m;
+        mls_point(J, xp, B.rw, B.alpha, lane, true, m, err);
+        float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (m.active) {
+            const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
+            if (l < 0) err |= FLAG_WINDOW;
+            else mom = P.mwin[B.win_off + l];
         }
-        // p = c_s^2 rho; tau = rho nu (grad u + grad u^T)
+        const double v[10] = {gsum(m.phi * (double)mom.x),
+                              gsum(m.gr[0] * (double)mom.y), gsum(m.gr[1] * (double)mom.y), gsum(m.gr[2] * (double)mom.y),
+                              gsum(m.gr[0] * (double)mom.z), gsum(m.gr[1] * (double)mom.z), gsum(m.gr[2] * (double)mom.z),
+                              gsum(m.gr[0] * (double)mom.w), gsum(m.gr[1] * (double)mom.w), gsum(m.gr[2] * (double)mom.w)};
+        if (lane == 0)
+            for (int i = 0; i < 10; ++i) probe[grp][i] = v[i];
+    }
+    if (err) atomicOr(P.flags + B.job, err);
+    __syncthreads();
+    double Ft[3] = {0, 0, 0}, Mt[3] = {0, 0, 0};
+    if (t < B.nt && side == 0 && lane == 0) {
+        // p = c_s^2 rho, tau = rho nu (grad u + grad u^T); grad u [i][j] = probe[1 + 3 i + j]
+        const double* pp = probe[grp];
+        const double* pm = probe[grp + 1];
         const double nu = J.nu;
-        const double rp = 1.0 + drho_s[0], rm = 1.0 + drho_s[1];
-        const double dp = (drho_s[0] - drho_s[1]) * (1.0 / 3.0);
+        const double rp = 1.0 + pp[0], rm = 1.0 + pm[0];
+        const double dp = (pp[0] - pm[0]) * (1.0 / 3.0);
         for (int i = 0; i < 3; ++i) {
             double tn = 0.0;
             for (int j = 0; j < 3; ++j)
-                tn += (rp * nu * (gu[0][i][j] + gu[0][j][i]) - rm * nu * (gu[1][i][j] + gu[1][j][i])) * nrm[j];
+                tn += (rp * nu * (pp[1 + 3 * i + j] + pp[1 + 3 * j + i]) -
+                       rm * nu * (pm[1 + 3 * i + j] + pm[1 + 3 * j + i])) * nrm[j];
             Ft[i] = (-dp * nrm[i] + tn) * A;
         }
-        if (lane == 0)
-            for (int i = 0; i < 3; ++i) P.fext[3 * (B.t0 + t) + i] = Ft[i];
-        const double* ref = B.rigid ? S.X : S.centre;
-        const double rr[3] = {cen[0] - ref[0], cen[1] - ref[1], cen[2] - ref[2]};
-        cross3(rr, Ft, Mt);
+        for (int i = 0; i < 3; ++i) P.fext[3 * (B.t0 + t) + i] = Ft[i];
+        if (!B.rigid) {
+            // volume penalty (Eq. volFor, restoring): k_v (1 - V/V0) n_t A_t, a third per vertex
+            const double vs = B.kv == 0.0 ? 0.0 : B.kv * (1.0 - S.V / B.V0) * (1.0 / 6.0);
+            for (int i = 0; i < 3; ++i) P.fvol[3 * (B.t0 + t) + i] = vs * N[i];
+        } else {
+            const double rr[3] = {cen[0] - S.X[0], cen[1] - S.X[1], cen[2] - S.X[2]};
+            cross3(rr, Ft, Mt);
+        }
     }
-    if (lane == 0)
-        for (int i = 0; i < 3; ++i) { red[grp][i] = Ft[i]; red[grp][3 + i] = Mt[i]; }
-    if (err) atomicOr(P.flags + B.job, err);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double part[6] = {0, 0, 0, 0, 0, 0};
-    for (int g = 0; g < MLS_PER_BLOCK; ++g)
-        for (int i = 0; i < 6; ++i) part[i] += red[g][i];
-    double tot[6];
-    if (!last_block_sum(P, B, blk, B.nblk_t, &S.counter_t, part, 6, tot)) return;
-    for (int i = 0; i < 3; ++i) { S.F[i] = tot[i]; S.M[i] = tot[3 + i]; }
     if (!B.rigid) return;
+    if (side == 0 && lane == 0)
+        for (int i = 0; i < 3; ++i) { red[k][i] = Ft[i]; red[k][3 + i] = Mt[i]; }
+    __syncthreads();
+    double part[6] = {0, 0, 0, 0, 0, 0};
+    for (int g = 0; g < TRI_PER_BLOCK; ++g)
+        for (int i = 0; i < 6; ++i) part[i] += red[g][i];
+    const int op[6] = {0, 0, 0, 0, 0, 0};
+    double tot[6];
+    if (!last_block_reduce(P, B, blk, B.nblk_t, &S.counter_t, part, op, 6, tot)) return;
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < 3; ++i) { S.F[i] = tot[i]; S.M[i] = tot[3 + i]; }
     // Rigid body, Eqs. (linearVelRig), (angularVelRig): udot = F/m with net weight (m - V0) g,
     // omegadot = I_w^{-1} M with I_w = R I R^T.
     double F[3];
@@ -314,13 +439,13 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             double s = 0.0;
-            for (int k = 0; k < 3; ++k) s += B.Ib[3 * i + k] * S.R[3 * j + k];  // I R^T
+            for (int q = 0; q < 3; ++q) s += B.Ib[3 * i + q] * S.R[3 * j + q];  // I R^T
             IR[3 * i + j] = s;
         }
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             double s = 0.0;
-            for (int k = 0; k < 3; ++k) s += S.R[3 * i + k] * IR[3 * k + j];
+            for (int q = 0; q < 3; ++q) s += S.R[3 * i + q] * IR[3 * q + j];
             Iw[3 * i + j] = s;
         }
     // omegadot = Iw^{-1} M by the adjugate
@@ -359,7 +484,7 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             double s = 0.0;
-            for (int k = 0; k < 3; ++k) s += Rw[3 * i + k] * S.R[3 * k + j];
+            for (int q = 0; q < 3; ++q) s += Rw[3 * i + q] * S.R[3 * q + j];
             Rn[3 * i + j] = s;
         }
     bool fin = isfinite(det) && det != 0.0;
@@ -369,101 +494,44 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
 }
 
 // ---------------------------------------------------------------- vertices
-// Internal force of one incident element on vertex v (FP64).
-__device__ __forceinline__ void spring_on(const Pools& P, const BodyDev& B, int code, int v, double f[3]) {
-    const int e = code >> 1;
-    const int other = P.edge[2 * (B.e0 + e) + ((code & 1) ? 0 : 1)];
-    double xv[3], xo[3];
-    load3(P.x + 3 * (B.v0 + v), xv);
-    load3(P.x + 3 * (B.v0 + other), xo);
-    const double r[3] = {xv[0] - xo[0], xv[1] - xo[1], xv[2] - xo[2]};
-    const double l = sqrt(dot3(r, r));
-    // Eq. (strainFor)
-    const double s = -P.ks[B.e0 + e] * (l - P.l0[B.e0 + e]) / l;
-    f[0] += s * r[0]; f[1] += s * r[1]; f[2] += s * r[2];
-}
-
-// Bending: -k_b sin(theta - theta0) dtheta/dx_role, theta the signed angle between the outward
-// normals of the hinge's triangles (x1,x2,x3) and (x2,x1,x4) about the edge x1->x2.
-__device__ __forceinline__ void bend_on(const Pools& P, const BodyDev& B, int code, double f[3]) {
-    const int h = code >> 2, role = code & 3;
-    const int* hv = P.hinge + 4 * (B.e0 + h);
-    double x1[3], x2[3], x3[3], x4[3];
-    load3(P.x + 3 * (B.v0 + hv[0]), x1);
-    load3(P.x + 3 * (B.v0 + hv[1]), x2);
-    load3(P.x + 3 * (B.v0 + hv[2]), x3);
-    load3(P.x + 3 * (B.v0 + hv[3]), x4);
-    double e[3], p3[3], p4[3], q[3];
-    for (int a = 0; a < 3; ++a) { e[a] = x2[a] - x1[a]; p3[a] = x3[a] - x1[a]; p4[a] = x4[a] - x2[a]; q[a] = x1[a] - x2[a]; }
-    double N1[3], N2[3];
-    cross3(e, p3, N1);
-    cross3(q, p4, N2);
-    const double le2 = dot3(e, e), le = sqrt(le2);
-    const double a1 = sqrt(dot3(N1, N1)), a2 = sqrt(dot3(N2, N2));
-    const double n1[3] = {N1[0] / a1, N1[1] / a1, N1[2] / a1};
-    const double n2[3] = {N2[0] / a2, N2[1] / a2, N2[2] / a2};
-    double c12[3];
-    cross3(n1, n2, c12);
-    const double theta = atan2(dot3(c12, e) / le, dot3(n1, n2));
-    // heights of x3, x4 over the edge line and foot-point parameters along x1->x2
-    const double h3 = a1 / le, h4 = a2 / le;
-    double d4[3] = {x4[0] - x1[0], x4[1] - x1[1], x4[2] - x1[2]};
-    const double t3 = dot3(p3, e) / le2, t4 = dot3(d4, e) / le2;
-    double g[3];
-    for (int a = 0; a < 3; ++a) {
-        const double g3 = -n1[a] / h3, g4 = -n2[a] / h4;
-        g[a] = role == 2 ? g3
-             : role == 3 ? g4
-             : role == 0 ? (t3 - 1.0) * g3 + (t4 - 1.0) * g4
-                         : -t3 * g3 - t4 * g4;
-    }
-    const double s = -B.kb * sin(theta - P.theta0[B.e0 + h]);
-    f[0] += s * g[0]; f[1] += s * g[1]; f[2] += s * g[2];
-}
+__device__ __forceinline__ int box_lo(double v) { return (int)floor(fmin(fmax(v, -1e7), 1e7)); }
+__device__ __forceinline__ int box_hi(double v) { return (int)ceil(fmin(fmax(v, -1e7), 1e7)); }
 
 __global__ void __launch_bounds__(256) k_vertices(Pools P) {
     const int b = P.blk_body_v[blockIdx.x];
     const BodyDev& B = P.bodies[b];
     const JobDev& J = P.jobs[B.job];
+    BodyState& S = P.bstate[b];
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_v0;
     const int v = blk * MLS_PER_BLOCK + grp;
-    __shared__ double box[MLS_PER_BLOCK][9];
-    BodyState& S = P.bstate[b];
+    __shared__ int box[MLS_PER_BLOCK][6];
     int err = 0;
-    double xn[3] = {0, 0, 0};
-    const bool valid = v < B.nv;
-    if (valid) {
+    int bl[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, bh[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
+    if (v < B.nv) {
         const long long gv = B.v0 + v;
+        // gathered forces: a third of each incident triangle's probe force, its volume force,
+        // the spring and bending forces of every incident hinge
         double f[3] = {0.0, 0.0, 0.0};
-        // external: a third of every incident triangle's probe force
         const int t_beg = P.vt_ptr[B.vt_off + v], t_end = P.vt_ptr[B.vt_off + v + 1];
-        const double vs = B.rigid ? 0.0 : B.kv * (1.0 - S.V / B.V0) * (1.0 / 6.0);
-        for (int k = t_beg + lane; k < t_end; k += GROUP) {
-            const int t = P.vt_list[k];
-            for (int a = 0; a < 3; ++a) f[a] += P.fext[3 * (B.t0 + t) + a] * (1.0 / 3.0);
-            if (!B.rigid && B.kv != 0.0) {
-                // volume penalty (Eq. volFor, restoring): k_v (1 - V/V0) N_t / 6 per vertex
-                const int* tv = P.tri + 3 * (B.t0 + t);
-                double xa[3], xb_[3], xc[3], ab[3], ac[3], N[3];
-                load3(P.x + 3 * (B.v0 + tv[0]), xa);
-                load3(P.x + 3 * (B.v0 + tv[1]), xb_);
-                load3(P.x + 3 * (B.v0 + tv[2]), xc);
-                for (int a = 0; a < 3; ++a) { ab[a] = xb_[a] - xa[a]; ac[a] = xc[a] - xa[a]; }
-                cross3(ab, ac, N);
-                for (int a = 0; a < 3; ++a) f[a] += vs * N[a];
-            }
+        for (int q = t_beg + lane; q < t_end; q += GROUP) {
+            const long long t = B.t0 + P.vt_list[q];
+            for (int a = 0; a < 3; ++a) f[a] += P.fext[3 * t + a] * (1.0 / 3.0);
+            if (!B.rigid)
+                for (int a = 0; a < 3; ++a) f[a] += P.fvol[3 * t + a];
         }
         if (!B.rigid) {
-            const int e_beg = P.ve_ptr[B.ve_off + v], e_end = P.ve_ptr[B.ve_off + v + 1];
-            for (int k = e_beg + lane; k < e_end; k += GROUP) spring_on(P, B, P.ve_list[k], v, f);
-            if (B.kb != 0.0) {
-                const int h_beg = P.vh_ptr[B.vh_off + v], h_end = P.vh_ptr[B.vh_off + v + 1];
-                for (int k = h_beg + lane; k < h_end; k += GROUP) bend_on(P, B, P.vh_list[k], f);
+            const int h_beg = P.vh_ptr[B.vh_off + v], h_end = P.vh_ptr[B.vh_off + v + 1];
+            for (int q = h_beg + lane; q < h_end; q += GROUP) {
+                const int code = P.vh_list[q];
+                const double* fe = P.fedge + 15LL * (B.e0 + (code >> 2));
+                const int role = code & 3;
+                const double sgn = role == 0 ? 1.0 : (role == 1 ? -1.0 : 0.0);
+                for (int a = 0; a < 3; ++a) f[a] += sgn * fe[a] + fe[3 + 3 * role + a];
             }
         }
         const double F0 = gsum(f[0]), F1 = gsum(f[1]), F2 = gsum(f[2]);
-        double x[3];
+        double x[3], xn[3];
         load3(P.x + 3 * gv, x);
         if (!B.rigid) {
             // tentative velocity: fluid velocity at the vertex from f^{n+1}
@@ -478,19 +546,20 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
             const double u0[3] = {gsum(m.phi * (double)mom.y), gsum(m.phi * (double)mom.z),
                                   gsum(m.phi * (double)mom.w)};
             const double Fv[3] = {F0, F1, F2};
-            double dx[3], un[3];
+            double un[3];
             for (int a = 0; a < 3; ++a) {
                 const double acc = Fv[a] / B.mv;
+                double dx;
                 if (B.integrator == 1) {
                     // Eqs. (verletPos), (verletVel), (verletPos) as printed, in displacement form
                     un[a] = 1.5 * (u0[a] + 0.5 * acc) - 0.5 * (x[a] - P.xprev[3 * gv + a]);
-                    dx[a] = un[a] + 0.5 * acc;
+                    dx = un[a] + 0.5 * acc;
                 } else {
                     // Eq. (verletPos); vertex velocity = displacement of the step
-                    dx[a] = u0[a] + 0.5 * acc;
-                    un[a] = dx[a];
+                    dx = u0[a] + 0.5 * acc;
+                    un[a] = dx;
                 }
-                xn[a] = x[a] + dx[a];
+                xn[a] = x[a] + dx;
             }
             if (lane == 0)
                 for (int a = 0; a < 3; ++a) {
@@ -514,81 +583,76 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
                     P.fv[3 * gv + a] = a == 0 ? F0 : (a == 1 ? F1 : F2);
                 }
         }
-        if (!(isfinite(xn[0]) && isfinite(xn[1]) && isfinite(xn[2]))) err |= FLAG_NONFINITE;
+        if (!(isfinite(xn[0]) && isfinite(xn[1]) && isfinite(xn[2])) ||
+            fabs(xn[0]) > 1e7 || fabs(xn[1]) > 1e7 || fabs(xn[2]) > 1e7)
+            err |= FLAG_NONFINITE;
+        for (int a = 0; a < 3; ++a) { bl[a] = box_lo(xn[a]); bh[a] = box_hi(xn[a]); }
     }
-    if (lane == 0) {
-        for (int a = 0; a < 3; ++a) {
-            box[grp][a] = valid ? xn[a] : 1e300;
-            box[grp][3 + a] = valid ? xn[a] : -1e300;
-            box[grp][6 + a] = valid ? xn[a] : 0.0;
-        }
-    }
+    if (lane == 0)
+        for (int a = 0; a < 3; ++a) { box[grp][a] = bl[a]; box[grp][3 + a] = bh[a]; }
     if (err) atomicOr(P.flags + B.job, err);
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    double part[9];
-    for (int a = 0; a < 3; ++a) { part[a] = 1e300; part[3 + a] = -1e300; part[6 + a] = 0.0; }
-    for (int g = 0; g < MLS_PER_BLOCK; ++g)
+    if (threadIdx.x == 0) {
+        for (int g = 1; g < MLS_PER_BLOCK; ++g)
+            for (int a = 0; a < 3; ++a) { box[0][a] = min(box[0][a], box[g][a]); box[0][3 + a] = max(box[0][3 + a], box[g][3 + a]); }
         for (int a = 0; a < 3; ++a) {
-            part[a] = fmin(part[a], box[g][a]);
-            part[3 + a] = fmax(part[3 + a], box[g][3 + a]);
-            part[6 + a] += box[g][6 + a];
-        }
-    // min/max are order independent; the sums are taken in block order by the last block
-    double* slot = P.partial + 16LL * (B.red_slot + blk);
-    for (int i = 0; i < 9; ++i) slot[i] = part[i];
-    __threadfence();
-    if (atomicAdd(&S.counter_v, 1) != B.nblk_v - 1) return;
-    __threadfence();
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, sum[3] = {0, 0, 0};
-    for (int k = 0; k < B.nblk_v; ++k) {
-        const double* p = P.partial + 16LL * (B.red_slot + k);
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], agent_load(p + a));
-            hi[a] = fmax(hi[a], agent_load(p + 3 + a));
-            sum[a] += agent_load(p + 6 + a);
+            atomicMin(&S.bmin[a], box[0][a]);
+            atomicMax(&S.bmax[a], box[0][3 + a]);
         }
     }
-    S.counter_v = 0;
-    // A runaway body keeps its last valid window: coordinates are converted to int only
-    // when they are finite and far inside the int range.
-    for (int a = 0; a < 3; ++a)
-        if (!(isfinite(lo[a]) && isfinite(hi[a]) && fabs(lo[a]) < 1e7 && fabs(hi[a]) < 1e7)) {
-            atomicOr(P.flags + B.job, FLAG_NONFINITE);
-            return;
-        }
-    for (int a = 0; a < 3; ++a) S.centre[a] = sum[a] / B.nv;
-    // force window of the next step: bounding box plus margin
-    WinDesc d;
-    const int dims[3] = {J.nx, J.ny, J.nz};
-    int flag = 0;
-    for (int a = 0; a < 3; ++a) {
-        int l = (int)floor(lo[a]) - WIN_MARGIN, h = (int)ceil(hi[a]) + WIN_MARGIN;
-        if (J.bc[2 * a] == 0) {
-            int w = h - l + 1;
-            if (w >= dims[a]) { d.o[a] = 0; d.w[a] = dims[a]; }
-            else { int o = l % dims[a]; if (o < 0) o += dims[a]; d.o[a] = o; d.w[a] = w; }
-        } else {
-            if (l < 0) l = 0;
-            if (h > dims[a] - 1) h = dims[a] - 1;
-            d.o[a] = l;
-            d.w[a] = h >= l ? h - l + 1 : 1;
-        }
-        if (d.w[a] > B.win_cap[a]) { flag |= FLAG_WINDOW; d.w[a] = B.win_cap[a]; }
-        if (d.w[a] < 1) d.w[a] = 1;
-    }
-    P.fdesc[b] = d;
-    if (flag) atomicOr(P.flags + B.job, flag);
 }
 
-void launch_centroids(const Pools& P, int nblocks, hipStream_t s) {
-    if (nblocks > 0) hipLaunchKernelGGL(k_centroids, dim3(nblocks), dim3(256), 0, s, P);
+// ---------------------------------------------------------------- reported totals (membranes)
+// FP64 hydrodynamic force and torque of the last step, torque about the vertex mean of x^n
+// (held in xprev after the update).  One block, fixed-shape tree: reproducible.
+__global__ void __launch_bounds__(256) k_body_totals(Pools P, int b, double* out) {
+    const BodyDev& B = P.bodies[b];
+    __shared__ double red[7][256];
+    const int t = threadIdx.x;
+    double c[3] = {0, 0, 0};
+    for (int v = t; v < B.nv; v += 256)
+        for (int a = 0; a < 3; ++a) c[a] += P.xprev[3 * (B.v0 + v) + a];
+    for (int a = 0; a < 3; ++a) red[a][t] = c[a];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) for (int a = 0; a < 3; ++a) red[a][t] += red[a][t + w];
+        __syncthreads();
+    }
+    const double ctr[3] = {red[0][0] / B.nv, red[1][0] / B.nv, red[2][0] / B.nv};
+    __syncthreads();
+    double F[3] = {0, 0, 0}, M[3] = {0, 0, 0};
+    for (int q = t; q < B.nt; q += 256) {
+        const int* tv = P.tri + 3 * (B.t0 + q);
+        double cen[3], f[3], m[3];
+        for (int a = 0; a < 3; ++a) {
+            cen[a] = (P.xprev[3 * (B.v0 + tv[0]) + a] + P.xprev[3 * (B.v0 + tv[1]) + a] +
+                      P.xprev[3 * (B.v0 + tv[2]) + a]) * (1.0 / 3.0) - ctr[a];
+            f[a] = P.fext[3 * (B.t0 + q) + a];
+        }
+        cross3(cen, f, m);
+        for (int a = 0; a < 3; ++a) { F[a] += f[a]; M[a] += m[a]; }
+    }
+    for (int a = 0; a < 3; ++a) { red[a][t] = F[a]; red[3 + a][t] = M[a]; }
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) for (int a = 0; a < 6; ++a) red[a][t] += red[a][t + w];
+        __syncthreads();
+    }
+    if (t < 6) out[t] = red[t][0];
+}
+
+void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, hipStream_t s) {
+    if (nblk_tri + nblk_edge > 0)
+        hipLaunchKernelGGL(k_centroids, dim3(nblk_tri + nblk_edge), dim3(256), 0, s, P, nblk_tri);
 }
 void launch_triangles(const Pools& P, int nblocks, hipStream_t s) {
     if (nblocks > 0) hipLaunchKernelGGL(k_triangles, dim3(nblocks), dim3(256), 0, s, P);
 }
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s) {
     if (nblocks > 0) hipLaunchKernelGGL(k_vertices, dim3(nblocks), dim3(256), 0, s, P);
+}
+void launch_body_totals(const Pools& P, int body, double* out6, hipStream_t s) {
+    hipLaunchKernelGGL(k_body_totals, dim3(1), dim3(256), 0, s, P, body, out6);
 }
 
 }  // namespace lbib

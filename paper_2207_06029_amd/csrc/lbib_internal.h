@@ -106,10 +106,10 @@ struct BodyDev {
     long long win_off;          // offset of the body's windows in the window pools (nodes)
     int win_cap[3];             // reserved window extent per axis
     int red_slot;               // offset of this body's block partials
-    // CSR of incident elements per vertex, offsets into the incidence pools
-    long long vt_off, ve_off, vh_off;
-    // first block of this body in the centroid / triangle / vertex grids and block counts
-    int blk_c0, nblk_c, blk_t0, nblk_t, blk_v0, nblk_v, pad2, pad3;
+    // CSR of incident triangles and hinge roles per vertex: offsets into the pointer pools
+    long long vt_off, vh_off;
+    // first block of this body in the centroid / edge / triangle / vertex grids, block counts
+    int blk_c0, nblk_c, blk_e0, nblk_e, blk_t0, nblk_t, blk_v0, nblk_v;
     double kb, kv, mv, V0, mass;
     double rw, alpha, probe, shell_h;
     double gravity[3];
@@ -118,12 +118,14 @@ struct BodyDev {
 
 // per-body mutable scalars (device)
 struct BodyState {
-    double V;          // enclosed volume at x^n (deformable)
-    double centre[3];  // vertex mean (deformable) used as torque reference
-    double F[3], M[3]; // hydrodynamic force / torque totals of the last step
+    double V;          // enclosed volume at x^n (membranes with a volume penalty)
+    double F[3], M[3]; // rigid bodies: hydrodynamic force / torque totals of the last step
     // rigid body
     double X[3], R[9], u[3], u1[3], om[3], om1[3];
-    int counter_c, counter_t, counter_v, pad;
+    int counter_c, counter_t, pad0, pad1;
+    // integer bounding box of the vertices (floor of minima, ceil of maxima), accumulated with
+    // order-independent atomics by the vertex kernel; it sets the next step's force window
+    int bmin[3], bmax[3];
 };
 
 // All device pools of one batch.  Kernels take this by value.
@@ -133,7 +135,8 @@ struct Pools {
     const JobDev* jobs;
     const int* tile_job;
     const BodyDev* bodies;
-    const int* blk_body_c;   // block -> body for the centroid kernel
+    const int* blk_body_c;   // block -> body for the centroid kernel (triangle blocks)
+    const int* blk_body_e;   // block -> body for the edge blocks of the centroid kernel
     const int* blk_body_t;
     const int* blk_body_v;
     double* x;               // [3 nv] positions x^n (all bodies concatenated)
@@ -149,11 +152,11 @@ struct Pools {
     const double* theta0;    // [ne]
     const int* vt_ptr;       // [nv+1 per body] incident triangles
     const int* vt_list;
-    const int* ve_ptr;       // incident edges: 2*edge + (vertex is the second end)
-    const int* ve_list;
-    const int* vh_ptr;       // incident hinges: 4*hinge + role
+    const int* vh_ptr;       // [nv+1 per body] incident hinges: 4*hinge + role
     const int* vh_list;
     double* fext;            // [3 nt] hydrodynamic force per triangle
+    double* fvol;            // [3 nt] volume-penalty force per vertex of each triangle
+    double* fedge;           // [15 ne] spring force on x1, bending force on x1..x4 per hinge
     long long* fwin;         // force windows, 3 components x window nodes (fixed point)
     float4* mwin;            // moment windows (rho - 1, u*)
     WinDesc* fdesc;          // force-window layout of the current step, per body
@@ -184,8 +187,10 @@ void launch_init_eq(int job, long long n, const double* rho, const double* u, do
                     hipStream_t s);
 
 // lbib_ib.hip
-void launch_centroids(const Pools& P, int nblocks, hipStream_t s);
+void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, hipStream_t s);
 void launch_triangles(const Pools& P, int nblocks, hipStream_t s);
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s);
+void launch_body_totals(const Pools& P, int body, double* out6, hipStream_t s);
+constexpr int TRI_PER_BLOCK = 4;  // probe kernel: two 32-lane groups (+/- probe) per triangle
 
 }  // namespace lbib

@@ -33,7 +33,7 @@ struct HostBody {
     std::vector<double> x, xprev, uv, fv, xb;
     std::vector<int> tri, edge, hinge;
     std::vector<double> l0, ks, theta0;
-    std::vector<int> vt_ptr, vt_list, ve_ptr, ve_list, vh_ptr, vh_list;
+    std::vector<int> vt_ptr, vt_list, vh_ptr, vh_list;   // incident triangles / hinge roles (CSR)
     double V0 = 0, S0 = 0, mv = 0, mass = 0, rbound = 0;
     double X0[3] = {0, 0, 0};
     double Ib[9] = {0};
@@ -61,7 +61,7 @@ struct Batch {
     std::vector<HostBody> hbodies;
     std::vector<BodyDev> host_bodies;
     int nbodies = 0;
-    int nblk_c = 0, nblk_t = 0, nblk_v = 0;
+    int nblk_c = 0, nblk_e = 0, nblk_t = 0, nblk_v = 0;
     long long max_cap = 0, max_red = 0;
     Pools P{};
     bool cur_b = false;        // buffer holding the latest post-collision state
@@ -75,7 +75,10 @@ struct Batch {
     hipStream_t capture_stream = nullptr;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_events, step_events;
+    std::vector<hipEvent_t> event_pool;   // created once, reused across timing windows
+    size_t event_next = 0;
     long long step_event_steps = 0;
+    lbib_status next_event(hipEvent_t* e);
 
     void job_from_desc(const lbib_lattice_desc& d, JobDev& J);
     lbib_status create_lattices(const std::vector<lbib_lattice_desc>& descs, int storage,

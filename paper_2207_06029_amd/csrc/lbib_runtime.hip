@@ -213,31 +213,21 @@ lbib_status build_body(const lbib_body_desc& d, const double* xyz, int nv, const
     hb.mv = d.mass_ratio * d.thickness * S0 / nv;
     // incidence lists (CSR) per vertex
     hb.vt_ptr.assign(nv + 1, 0);
-    hb.ve_ptr.assign(nv + 1, 0);
     hb.vh_ptr.assign(nv + 1, 0);
     for (int t = 0; t < nt; ++t) for (int j = 0; j < 3; ++j) hb.vt_ptr[tri[3 * t + j] + 1]++;
-    for (int e = 0; e < ne; ++e) {
-        hb.ve_ptr[hb.edge[2 * e] + 1]++;
-        hb.ve_ptr[hb.edge[2 * e + 1] + 1]++;
+    for (int e = 0; e < ne; ++e)
         for (int r = 0; r < 4; ++r) hb.vh_ptr[hb.hinge[4 * e + r] + 1]++;
-    }
     for (int v = 0; v < nv; ++v) {
         hb.vt_ptr[v + 1] += hb.vt_ptr[v];
-        hb.ve_ptr[v + 1] += hb.ve_ptr[v];
         hb.vh_ptr[v + 1] += hb.vh_ptr[v];
     }
     hb.vt_list.resize(hb.vt_ptr[nv]);
-    hb.ve_list.resize(hb.ve_ptr[nv]);
     hb.vh_list.resize(hb.vh_ptr[nv]);
     {
-        std::vector<int> ft(hb.vt_ptr.begin(), hb.vt_ptr.end() - 1), fe(hb.ve_ptr.begin(), hb.ve_ptr.end() - 1),
-            fh(hb.vh_ptr.begin(), hb.vh_ptr.end() - 1);
+        std::vector<int> ft(hb.vt_ptr.begin(), hb.vt_ptr.end() - 1), fh(hb.vh_ptr.begin(), hb.vh_ptr.end() - 1);
         for (int t = 0; t < nt; ++t) for (int j = 0; j < 3; ++j) hb.vt_list[ft[tri[3 * t + j]]++] = t;
-        for (int e = 0; e < ne; ++e) {
-            hb.ve_list[fe[hb.edge[2 * e]]++] = 2 * e;
-            hb.ve_list[fe[hb.edge[2 * e + 1]]++] = 2 * e + 1;
+        for (int e = 0; e < ne; ++e)
             for (int r = 0; r < 4; ++r) hb.vh_list[fh[hb.hinge[4 * e + r]]++] = 4 * e + r;
-        }
     }
     // rigid mass properties: signed tetrahedra from the origin, then second moments about the
     // volume centroid; inertia I = rho_s (tr(C) 1 - C)
@@ -417,14 +407,14 @@ lbib_status Batch::rebuild_bodies() {
     std::stable_sort(hbodies.begin(), hbodies.end(), [](const HostBody& a, const HostBody& b) { return a.job < b.job; });
     for (auto& J : jobs) { J.body0 = 0; J.nbodies = 0; }
     std::vector<BodyDev> bd(hbodies.size());
-    std::vector<int> bc, bt, bv;
+    std::vector<int> bc, be, bt, bv;
     std::vector<double> x, xprev, uv, xb, l0, ks, th0;
-    std::vector<int> tri, edge, hinge, vtp, vtl, vep, vel, vhp, vhl;
+    std::vector<int> tri, edge, hinge, vtp, vtl, vhp, vhl;
     std::vector<WinDesc> fd(hbodies.size());
     std::vector<BodyState> bs(hbodies.size());
     long long v0 = 0, t0 = 0, e0 = 0, woff = 0, red = 0;
     max_cap = 0;
-    nblk_c = nblk_t = nblk_v = 0;
+    nblk_c = nblk_e = nblk_t = nblk_v = 0;
     for (size_t i = 0; i < hbodies.size(); ++i) {
         HostBody& h = hbodies[i];
         JobDev& J = jobs[h.job];
@@ -436,7 +426,6 @@ lbib_status Batch::rebuild_bodies() {
         B.nv = h.nv; B.nt = h.nt; B.ne = h.ne;
         B.v0 = v0; B.t0 = t0; B.e0 = e0;
         B.vt_off = v0 + (long long)i;  // CSR pointer arrays hold nv+1 entries per body
-        B.ve_off = B.vt_off;
         B.vh_off = B.vt_off;
         B.kb = h.desc.kb; B.kv = h.desc.kv; B.mv = h.mv; B.V0 = h.V0; B.mass = h.mass;
         B.rw = h.desc.mls_rw; B.alpha = h.desc.mls_alpha; B.probe = h.desc.probe_len; B.shell_h = h.desc.shell_h;
@@ -450,14 +439,20 @@ lbib_status Batch::rebuild_bodies() {
         B.win_off = woff;
         woff += capn;
         max_cap = std::max<long long>(max_cap, capn);
-        const int nbc = (h.nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbv = (h.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
+        const int nbc = (h.nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
+        const int nbt = (h.nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
+        const int nbv = (h.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
+        const int nbe = h.desc.rigid ? 0 : (h.ne + 255) / 256;
         B.blk_c0 = nblk_c; B.nblk_c = nbc; nblk_c += nbc;
-        B.blk_t0 = nblk_t; B.nblk_t = nbc; nblk_t += nbc;
+        B.blk_e0 = nblk_e; B.nblk_e = nbe; nblk_e += nbe;
+        B.blk_t0 = nblk_t; B.nblk_t = nbt; nblk_t += nbt;
         B.blk_v0 = nblk_v; B.nblk_v = nbv; nblk_v += nbv;
-        for (int k = 0; k < nbc; ++k) { bc.push_back((int)i); bt.push_back((int)i); }
+        for (int k = 0; k < nbc; ++k) bc.push_back((int)i);
+        for (int k = 0; k < nbe; ++k) be.push_back((int)i);
+        for (int k = 0; k < nbt; ++k) bt.push_back((int)i);
         for (int k = 0; k < nbv; ++k) bv.push_back((int)i);
         B.red_slot = (int)red;
-        red += std::max(nbc, nbv);
+        red += std::max(nbc, nbt);
         x.insert(x.end(), h.x.begin(), h.x.end());
         xprev.insert(xprev.end(), h.xprev.begin(), h.xprev.end());
         uv.insert(uv.end(), h.uv.begin(), h.uv.end());
@@ -469,32 +464,28 @@ lbib_status Batch::rebuild_bodies() {
         ks.insert(ks.end(), h.ks.begin(), h.ks.end());
         th0.insert(th0.end(), h.theta0.begin(), h.theta0.end());
         // CSR pointers are stored relative to this body's list offsets
-        const int ot = (int)vtl.size(), oe = (int)vel.size(), oh = (int)vhl.size();
+        const int ot = (int)vtl.size(), oh = (int)vhl.size();
         for (int v = 0; v <= h.nv; ++v) {
             vtp.push_back(ot + h.vt_ptr[v]);
-            vep.push_back(oe + h.ve_ptr[v]);
             vhp.push_back(oh + h.vh_ptr[v]);
         }
         vtl.insert(vtl.end(), h.vt_list.begin(), h.vt_list.end());
-        vel.insert(vel.end(), h.ve_list.begin(), h.ve_list.end());
         vhl.insert(vhl.end(), h.vh_list.begin(), h.vh_list.end());
         v0 += h.nv; t0 += h.nt; e0 += h.ne;
         // state
         BodyState& S = bs[i];
         std::memset(&S, 0, sizeof S);
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int v = 0; v < h.nv; ++v)
+            for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], h.x[3 * v + a]); hi[a] = std::max(hi[a], h.x[3 * v + a]); }
         if (h.has_state) S = h.state;
         else {
             S.V = h.V0;
             for (int k = 0; k < 9; ++k) S.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
             for (int a = 0; a < 3; ++a) S.X[a] = h.X0[a];
-            double c[3] = {0, 0, 0};
-            for (int v = 0; v < h.nv; ++v) for (int a = 0; a < 3; ++a) c[a] += h.x[3 * v + a];
-            for (int a = 0; a < 3; ++a) S.centre[a] = c[a] / h.nv;
+            for (int a = 0; a < 3; ++a) { S.bmin[a] = (int)std::floor(lo[a]); S.bmax[a] = (int)std::ceil(hi[a]); }
         }
-        S.counter_c = S.counter_t = S.counter_v = 0;
-        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        for (int v = 0; v < h.nv; ++v)
-            for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], h.x[3 * v + a]); hi[a] = std::max(hi[a], h.x[3 * v + a]); }
+        S.counter_c = S.counter_t = 0;
         bool over = false;
         fd[i] = h.has_state ? h.fdesc : window_for(J, lo, hi, B.win_cap, &over);
         if (over) return fail(LBIB_EDOMAIN, "body does not fit its window");
@@ -503,6 +494,7 @@ lbib_status Batch::rebuild_bodies() {
     max_red = red;
     if ((st = upload(arena, bd, (BodyDev**)&P.bodies, stream))) return st;
     if ((st = upload(arena, bc, (int**)&P.blk_body_c, stream))) return st;
+    if ((st = upload(arena, be, (int**)&P.blk_body_e, stream))) return st;
     if ((st = upload(arena, bt, (int**)&P.blk_body_t, stream))) return st;
     if ((st = upload(arena, bv, (int**)&P.blk_body_v, stream))) return st;
     if ((st = upload(arena, x, &P.x, stream))) return st;
@@ -522,12 +514,13 @@ lbib_status Batch::rebuild_bodies() {
     if ((st = upload(arena, th0, (double**)&P.theta0, stream))) return st;
     if ((st = upload(arena, vtp, (int**)&P.vt_ptr, stream))) return st;
     if ((st = upload(arena, vtl, (int**)&P.vt_list, stream))) return st;
-    if ((st = upload(arena, vep, (int**)&P.ve_ptr, stream))) return st;
-    if ((st = upload(arena, vel, (int**)&P.ve_list, stream))) return st;
     if ((st = upload(arena, vhp, (int**)&P.vh_ptr, stream))) return st;
     if ((st = upload(arena, vhl, (int**)&P.vh_list, stream))) return st;
     std::vector<double> fe(3 * (size_t)std::max<long long>(t0, 1), 0.0);
     if ((st = upload(arena, fe, &P.fext, stream))) return st;
+    if ((st = upload(arena, fe, &P.fvol, stream))) return st;
+    std::vector<double> fedge(15 * (size_t)std::max<long long>(e0, 1), 0.0);
+    if ((st = upload(arena, fedge, &P.fedge, stream))) return st;
     void* p;
     if ((st = arena.alloc(sizeof(long long) * 3 * std::max<long long>(woff, 1), &p))) return st;
     P.fwin = (long long*)p;
@@ -692,11 +685,12 @@ lbib_status Batch::prime() {
 
 lbib_status Batch::enqueue_step(bool collide) {
     const bool bodies = collide && nbodies > 0;
-    if (bodies) launch_centroids(P, nblk_c, stream);
+    if (bodies) launch_centroids(P, nblk_c, nblk_e, stream);
     if (timing) {
         hipEvent_t a, b;
-        HIP_TRY(hipEventCreate(&a));
-        HIP_TRY(hipEventCreate(&b));
+        lbib_status st = next_event(&a);
+        if (!st) st = next_event(&b);
+        if (st) return st;
         HIP_TRY(hipEventRecord(a, stream));
         launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, stream);
         HIP_TRY(hipEventRecord(b, stream));
@@ -735,8 +729,7 @@ lbib_status Batch::step(int nsteps, bool collide) {
     }
     hipEvent_t s0 = nullptr, s1 = nullptr;
     if (timing) {
-        HIP_TRY(hipEventCreate(&s0));
-        HIP_TRY(hipEventCreate(&s1));
+        if ((st = next_event(&s0)) || (st = next_event(&s1))) return st;
         HIP_TRY(hipEventRecord(s0, stream));
     }
     for (int i = 0; i < nsteps; ++i) {
@@ -789,17 +782,29 @@ lbib_status Batch::kernel_time(int kernel, double* ms, int64_t* count) {
     return LBIB_OK;
 }
 
+lbib_status Batch::next_event(hipEvent_t* e) {
+    if (event_next == event_pool.size()) {
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t ev;
+            HIP_TRY(hipEventCreate(&ev));
+            event_pool.push_back(ev);
+        }
+    }
+    *e = event_pool[event_next++];
+    return LBIB_OK;
+}
+
 void Batch::clear_events() {
-    for (auto& pr : sweep_events) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
-    for (auto& pr : step_events) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
     sweep_events.clear();
     step_events.clear();
+    event_next = 0;
     step_event_steps = 0;
 }
 
 Batch::~Batch() {
     if (stream) hipStreamSynchronize(stream);
     clear_events();
+    for (hipEvent_t e : event_pool) hipEventDestroy(e);
     if (graph_exec) hipGraphExecDestroy(graph_exec);
     if (graph) hipGraphDestroy(graph);
     if (capture_stream) hipStreamDestroy(capture_stream);
@@ -819,10 +824,23 @@ lbib_status Batch::body_forces(int bi, double* fv, double* F, double* M) {
     HIP_TRY(hipStreamSynchronize(stream));
     const BodyDev& B = host_bodies[bi];
     if (fv) HIP_TRY(hipMemcpy(fv, P.fv + 3 * B.v0, sizeof(double) * 3 * B.nv, hipMemcpyDeviceToHost));
-    BodyState S;
-    HIP_TRY(hipMemcpy(&S, P.bstate + bi, sizeof S, hipMemcpyDeviceToHost));
-    if (F) for (int a = 0; a < 3; ++a) F[a] = S.F[a];
-    if (M) for (int a = 0; a < 3; ++a) M[a] = S.M[a];
+    double tot[6];
+    if (B.rigid) {
+        BodyState S;
+        HIP_TRY(hipMemcpy(&S, P.bstate + bi, sizeof S, hipMemcpyDeviceToHost));
+        for (int a = 0; a < 3; ++a) { tot[a] = S.F[a]; tot[3 + a] = S.M[a]; }
+    } else {
+        // membranes: totals of the last step's probe forces, reduced on the device in FP64
+        double* d = nullptr;
+        HIP_TRY(hipMalloc(&d, sizeof(double) * 6));
+        launch_body_totals(P, bi, d, stream);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(tot, d, sizeof tot, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        hipFree(d);
+    }
+    if (F) for (int a = 0; a < 3; ++a) F[a] = tot[a];
+    if (M) for (int a = 0; a < 3; ++a) M[a] = tot[3 + a];
     return LBIB_OK;
 }
 
