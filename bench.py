@@ -61,6 +61,139 @@ def calibrate_copy(nbytes: int, reps: int) -> None:
     print(json.dumps({"calibration_copy_bytes": nbytes, "reps": reps}))
 
 
+def bench_batch(args) -> dict:
+    """64 capsule-in-shear jobs in shared launches (FP16 shifted storage, hipGraph, autotuned
+    sweep shape) against the plain form: the same jobs one at a time with FP32 storage."""
+    import torch
+    from paper_2207_06029_amd import api
+    from paper_2207_06029_amd import inputs as I
+    jobs = I.capsule_batch(seed=0, njobs=64, storage=I.STORE_F16, steps=2000)
+    nodes = sum(j.lattice.n for j in jobs)
+    stream = torch.cuda.current_stream()
+    bt = api.Batch(jobs, storage=I.STORE_F16, autotune=True, use_graph=True, stream=stream)
+    bt.step(args.warmup)
+    bt.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bt.sync()
+    per_step = wall / args.steps
+    # sweep-only timing of the batched launch (events around the sweep, no graph)
+    lat0 = bt.lattice(0)
+    lat0.set_timing(True)
+    bt.step(50)
+    sweep_ms, nsweep = lat0.kernel_time(0)
+    lat0.set_timing(False)
+    sweep_s = sweep_ms / nsweep / 1e3
+    bytes_sweep = 2 * 19 * 2 * nodes
+    # plain per-job form
+    plain_s = 0.0
+    k = max(10, args.steps // 10)
+    for idx, j in enumerate(jobs):
+        if idx % 16 == 0:
+            print(f"[batch] plain per-job form: job {idx}/{len(jobs)}", file=sys.stderr, flush=True)
+        lat = api.Lattice(j.lattice.__class__(**{**j.lattice.__dict__, "storage": I.STORE_F32}), stream=stream)
+        lat.add_body(j.body, j.xyz, j.tri)
+        lat.step(5)
+        lat.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(k)
+        torch.cuda.synchronize()
+        plain_s += (time.perf_counter() - t0) / k
+        lat.sync()
+        lat.destroy()
+    steps_job = jobs[0].steps
+    return {
+        "metric": METRIC, "mode": "batch",
+        "value": round(nodes / per_step / 1e6, 2), "unit": "MLUPS",
+        "jobs_per_hour": round(3600.0 / (per_step * steps_job) * len(jobs), 1),
+        "plain_jobs_per_hour": round(3600.0 / (plain_s * steps_job) * len(jobs), 1),
+        "plain_mlups": round(nodes / plain_s / 1e6, 2),
+        "ms_per_batched_step": round(per_step * 1e3, 4),
+        "launch_shape": list(bt.launch_shape()),
+        "roofline": {"bound": "hbm", "achieved": round(bytes_sweep / sweep_s / 1e9, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(bytes_sweep / sweep_s / 1e9 / PEAK_HBM_GBS, 4),
+                     "kernel": "k_sweep<half,collide> (64 jobs)", "bytes_per_launch": bytes_sweep,
+                     "avg_launch_us": round(sweep_s * 1e6, 3)},
+        "config": {"workload": "64 capsule-in-shear jobs, cubic edges from {32..96}, spheres and "
+                               "oblate capsules, level 3/4 meshes, FP16 shifted storage",
+                   "nodes_total": nodes, "steps_timed": args.steps},
+        "dtype": "f16-storage/f32-compute", "data": "synthetic", "n_gpus": 1,
+    }
+
+
+def bench_serve(args) -> dict:
+    """Poisson arrivals (mean 4 jobs/s) of capsule-shear and settling jobs served with
+    continuous batching and a device-memory budget; time-to-result percentiles and throughput,
+    then the same stream through a one-job-at-a-time FIFO of the plain FP32 form."""
+    import numpy as np
+    import torch
+    from paper_2207_06029_amd import api
+    from paper_2207_06029_amd import inputs as I
+
+    def run(stream_jobs, slots, storage, budget, tick):
+        srv = api.Server(hbm_budget_bytes=budget, max_slots=slots, steps_per_tick=tick,
+                         storage=storage, stream=torch.cuda.current_stream())
+        pending = sorted(stream_jobs, key=lambda j: j.arrival_s)
+        t_start = time.perf_counter()
+        done, nodes_steps = [], 0.0
+        i = 0
+        last_note = 0.0
+        while len(done) < len(pending):
+            now = time.perf_counter() - t_start
+            if now - last_note > 10.0:
+                st = srv.stats()
+                print(f"[serve slots={slots}] t={now:.0f}s submitted={i} done={len(done)} "
+                      f"resident={st['resident']} queued={st['queued']}", file=sys.stderr, flush=True)
+                last_note = now
+            while i < len(pending) and pending[i].arrival_s <= now:
+                srv.submit(pending[i])
+                i += 1
+            srv.tick()
+            for r in srv.poll():
+                done.append(r)
+            if i < len(pending) and srv.stats()["resident"] == 0 and srv.stats()["queued"] == 0:
+                time.sleep(max(0.0, pending[i].arrival_s - (time.perf_counter() - t_start)))
+            if time.perf_counter() - t_start > args.serve_window * 6 + 120:
+                break
+        wall = time.perf_counter() - t_start
+        st = srv.stats()
+        lat = np.array([(r["t_finish_ns"] - r["t_submit_ns"]) * 1e-9 for r in done])
+        ok = sum(1 for r in done if r["status"] == 0)
+        by_tag = {j.tag: j for j in pending}
+        failures = []
+        for r in done:
+            if r["status"] != 0:
+                j = by_tag[r["tag"]]
+                failures.append({"status": r["status"], "kind": j.kind, "dims": [j.lattice.nx, j.lattice.ny, j.lattice.nz],
+                                 "nv": int(len(j.xyz)), "mass_ratio": round(j.body.mass_ratio, 3),
+                                 "ks0": round(j.body.ks0, 5), "kb": round(j.body.kb, 6),
+                                 "tau": round(j.lattice.tau, 3), "steps_done": r["steps_done"]})
+        return {"jobs": len(done), "ok": ok, "failures": failures[:40], "wall_s": round(wall, 2),
+                "jobs_per_hour": round(len(done) / wall * 3600, 1),
+                "mlups": round(st["node_updates"] / wall / 1e6, 1),
+                "p50_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
+                "p99_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None}
+
+    jobs = I.serving_stream(seed=0, rate_per_s=4.0, window_s=args.serve_window,
+                            storage=I.STORE_F16)
+    served = run(jobs, slots=64, storage=I.STORE_F16, budget=32 << 30, tick=100)
+    plain = run(I.serving_stream(seed=0, rate_per_s=4.0, window_s=args.serve_window,
+                                 storage=I.STORE_F32), slots=1, storage=I.STORE_F32,
+                budget=32 << 30, tick=100)
+    return {"metric": METRIC, "mode": "serve", "value": served["jobs_per_hour"], "unit": "jobs/h",
+            "served": served, "plain_fifo": plain,
+            "config": {"workload": f"Poisson arrivals 4 jobs/s over {args.serve_window:.0f} s: "
+                                   "capsule-shear and settling jobs, lattices 48^3..128x64x128, "
+                                   "meshes 642-10242 vertices, 2000-10000 steps, FP16 storage, "
+                                   "32 GiB budget, 64 slots, 100 steps per tick"},
+            "dtype": "f16-storage/f32-compute", "data": "synthetic", "n_gpus": 1}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +204,8 @@ def main() -> int:
     ap.add_argument("--calib-copy", type=int, default=0, help="bytes: run only a copy of that size")
     ap.add_argument("--graph", action="store_true",
                     help="also time the same steps replayed from a captured hipGraph")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve"], default="plain")
+    ap.add_argument("--serve-window", type=float, default=60.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
@@ -78,6 +213,12 @@ def main() -> int:
         return 2
     if args.calib_copy:
         calibrate_copy(args.calib_copy, 10)
+        return 0
+    if args.mode == "batch":
+        print(json.dumps(bench_batch(args)))
+        return 0
+    if args.mode == "serve":
+        print(json.dumps(bench_serve(args)))
         return 0
 
     import torch

@@ -208,6 +208,9 @@ typedef struct {
     int32_t steps_per_tick;      /* steps every resident job advances per tick */
     int32_t storage;             /* lbib_storage of every job */
     int32_t use_graph;
+    int32_t dry_run;             /* 1: schedule only (admission, ticks, retirement) without any
+                                    device work; results carry no state.  For policy tests. */
+    int32_t pad;
 } lbib_server_opts;
 
 typedef struct {

@@ -53,7 +53,8 @@ class lbib_batch_opts(ctypes.Structure):
 class lbib_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("steps_per_tick", ctypes.c_int32), ("storage", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("dry_run", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class lbib_result(ctypes.Structure):

@@ -239,7 +239,7 @@ class Server:
     """lbib_server: continuous batching with memory-budget admission."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int, steps_per_tick: int,
-                 storage: int = 1, use_graph: bool = False, stream=None):
+                 storage: int = 1, use_graph: bool = False, stream=None, dry_run: bool = False):
         self._lib = L.load()
         o = L.lbib_server_opts()
         o.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -247,6 +247,7 @@ class Server:
         o.steps_per_tick = int(steps_per_tick)
         o.storage = int(storage)
         o.use_graph = int(bool(use_graph))
+        o.dry_run = int(bool(dry_run))
         h = ctypes.c_void_p()
         L.check(self._lib.lbib_server_create(ctypes.byref(o), _stream_handle(stream), ctypes.byref(h)))
         self._h = h

@@ -22,9 +22,23 @@
 
 namespace lbib {
 
+// Sum over the 32 lanes of an MLS group.  Lane exchanges xor 1 and xor 2 are quad permutes,
+// then row half-mirror and row mirror pair the 4- and 8-lane halves (after the previous levels
+// every lane of a block holds the same partial, so a mirror acts as an exchange), and the
+// 16-lane halves meet through a lane permute.  Each level adds the same two operands on both
+// partners, so every lane ends with the identical sum.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-    for (int o = 16; o >= 1; o >>= 1) v += __shfl_xor(v, o, GROUP);
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    v += __shfl_xor(v, 16, GROUP);
     return v;
 }
 
@@ -32,39 +46,32 @@ __device__ __forceinline__ double agent_load(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Shape functions of one point.  Output per lane: active (W > 0), wrapped node coordinates,
-// phi_k and (optionally) its gradient.  err receives FLAG_DOMAIN when a supporting node falls
-// on or behind a wall.
+// One MLS point, per lane: lane k < 27 owns node k of the 3x3x3 block around the nearest node.
+// mls_setup finds the node, its offset d = x_k - x, r = |d| / r_w and whether it supports the
+// point (r <= 1); the caller then issues its field loads, and mls_solve builds and solves the
+// moment system while those loads are in flight.
 struct MlsLane {
     bool active;
     int gx, gy, gz;
+    double d0, d1, d2, r;
     double phi;
     double gr[3];
 };
 
-__device__ __forceinline__ void mls_point(const JobDev& J, const double xp[3], double rw,
-                                          double alpha, int lane, bool want_grad, MlsLane& m,
-                                          int& err) {
+__device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], double rw, int lane,
+                                          MlsLane& m, int& err) {
     const int c0 = (int)floor(xp[0] + 0.5), c1 = (int)floor(xp[1] + 0.5), c2 = (int)floor(xp[2] + 0.5);
-    double W = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
     m.active = false;
-    int n0 = 0, n1 = 0, n2 = 0;
+    m.d0 = m.d1 = m.d2 = 0.0;
+    m.r = 2.0;
+    m.gr[0] = m.gr[1] = m.gr[2] = 0.0;
     if (lane < 27) {
-        n0 = c0 + lane % 3 - 1;
-        n1 = c1 + (lane / 3) % 3 - 1;
-        n2 = c2 + lane / 9 - 1;
-        d0 = n0 - xp[0];
-        d1 = n1 - xp[1];
-        d2 = n2 - xp[2];
-        const double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2) / rw;
-        if (r <= 1.0) {
-            const double q = r / alpha;
-            W = exp(-q * q);
-            m.active = true;
-        }
-    }
-    if (m.active) {
-        int nn[3] = {n0, n1, n2};
+        int nn[3] = {c0 + lane % 3 - 1, c1 + (lane / 3) % 3 - 1, c2 + lane / 9 - 1};
+        m.d0 = nn[0] - xp[0];
+        m.d1 = nn[1] - xp[1];
+        m.d2 = nn[2] - xp[2];
+        m.r = sqrt(m.d0 * m.d0 + m.d1 * m.d1 + m.d2 * m.d2) / rw;
+        m.active = m.r <= 1.0;
         const int dims[3] = {J.nx, J.ny, J.nz};
         for (int a = 0; a < 3; ++a) {
             const int bc = J.bc[2 * a];
@@ -73,33 +80,46 @@ __device__ __forceinline__ void mls_point(const JobDev& J, const double xp[3], d
                 if (nn[a] < 0) nn[a] += dims[a];
             } else {
                 const int lo = bc == 1 ? 1 : 0, hi = bc == 1 ? dims[a] - 2 : dims[a] - 1;
-                if (nn[a] < lo || nn[a] > hi) { err |= FLAG_DOMAIN; nn[a] = nn[a] < lo ? lo : hi; }
+                if (nn[a] < lo || nn[a] > hi) {
+                    if (m.active) err |= FLAG_DOMAIN;
+                    nn[a] = nn[a] < lo ? lo : hi;
+                }
             }
         }
         m.gx = nn[0]; m.gy = nn[1]; m.gz = nn[2];
     }
-    // A = sum W p p^T, p = (1, d)
+}
+
+// Shape functions phi_k = [A^{-1} W_k p_k]_0 and (optionally) their gradients, A = sum W p p^T,
+// p = (1, d), W = exp(-(r/alpha)^2) (Eqs. l2norm, intKernel).  FP64, Cholesky on every lane.
+__device__ __forceinline__ void mls_solve(MlsLane& m, double alpha, bool want_grad, int& err) {
+    double W = 0.0;
+    if (m.active) {
+        const double q = m.r / alpha;
+        W = exp(-q * q);
+    }
+    const double d0 = m.d0, d1 = m.d1, d2 = m.d2;
     const double a00 = gsum(W), a01 = gsum(W * d0), a02 = gsum(W * d1), a03 = gsum(W * d2);
     const double a11 = gsum(W * d0 * d0), a12 = gsum(W * d0 * d1), a13 = gsum(W * d0 * d2);
     const double a22 = gsum(W * d1 * d1), a23 = gsum(W * d1 * d2), a33 = gsum(W * d2 * d2);
-    // Cholesky A = L L^T
-    const double l00 = sqrt(a00);
-    const double l10 = a01 / l00, l20 = a02 / l00, l30 = a03 / l00;
-    const double l11 = sqrt(a11 - l10 * l10);
-    const double l21 = (a12 - l20 * l10) / l11, l31 = (a13 - l30 * l10) / l11;
-    const double l22 = sqrt(a22 - l20 * l20 - l21 * l21);
-    const double l32 = (a23 - l30 * l20 - l31 * l21) / l22;
-    const double l33 = sqrt(a33 - l30 * l30 - l31 * l31 - l32 * l32);
+    // Cholesky A = L L^T with reciprocal diagonals
+    const double l00 = sqrt(a00), i00 = 1.0 / l00;
+    const double l10 = a01 * i00, l20 = a02 * i00, l30 = a03 * i00;
+    const double l11 = sqrt(a11 - l10 * l10), i11 = 1.0 / l11;
+    const double l21 = (a12 - l20 * l10) * i11, l31 = (a13 - l30 * l10) * i11;
+    const double l22 = sqrt(a22 - l20 * l20 - l21 * l21), i22 = 1.0 / l22;
+    const double l32 = (a23 - l30 * l20 - l31 * l21) * i22;
+    const double l33 = sqrt(a33 - l30 * l30 - l31 * l31 - l32 * l32), i33 = 1.0 / l33;
     if (!(l33 > 0.0) || !(l22 > 0.0) || !(l11 > 0.0) || !(l00 > 0.0)) err |= FLAG_NONFINITE;
-    // v = A^{-1} p_k
-    const double y0 = 1.0 / l00;
-    const double y1 = (d0 - l10 * y0) / l11;
-    const double y2 = (d1 - l20 * y0 - l21 * y1) / l22;
-    const double y3 = (d2 - l30 * y0 - l31 * y1 - l32 * y2) / l33;
-    const double v3 = y3 / l33;
-    const double v2 = (y2 - l32 * v3) / l22;
-    const double v1 = (y1 - l21 * v2 - l31 * v3) / l11;
-    const double v0 = (y0 - l10 * v1 - l20 * v2 - l30 * v3) / l00;
+    // v = A^{-1} p_k: forward then back substitution
+    const double y0 = i00;
+    const double y1 = (d0 - l10 * y0) * i11;
+    const double y2 = (d1 - l20 * y0 - l21 * y1) * i22;
+    const double y3 = (d2 - l30 * y0 - l31 * y1 - l32 * y2) * i33;
+    const double v3 = y3 * i33;
+    const double v2 = (y2 - l32 * v3) * i22;
+    const double v1 = (y1 - l21 * v2 - l31 * v3) * i11;
+    const double v0 = (y0 - l10 * v1 - l20 * v2 - l30 * v3) * i00;
     m.phi = W * v0;
     if (want_grad) { m.gr[0] = W * v1; m.gr[1] = W * v2; m.gr[2] = W * v3; }
 }
@@ -263,25 +283,46 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri) {
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_c0;
     const int t = blk * MLS_PER_BLOCK + grp;
+    const bool live = t < B.nt;
     __shared__ double vol[MLS_PER_BLOCK];
+    __shared__ int sbox[6];
     int err = 0;
-    // this step's force window (every block derives the same descriptor; block 0 publishes it)
-    const int bmin[3] = {S.bmin[0], S.bmin[1], S.bmin[2]}, bmax[3] = {S.bmax[0], S.bmax[1], S.bmax[2]};
-    const WinDesc fd = window_from_box(J, B, bmin, bmax, err);
-    if (blk == 0 && threadIdx.x == 0) P.fdesc[b] = fd;
-    double Vt = 0.0;
-    if (t < B.nt) {
+    // triangle geometry at x^n and the desired velocity inputs, loaded before the window fold
+    // below so that their latency overlaps it
+    double xa[3] = {0, 0, 0}, xb_[3] = {0, 0, 0}, xc[3] = {0, 0, 0}, Ub[3] = {0, 0, 0};
+    if (live) {
         const int* tv = P.tri + 3 * (B.t0 + t);
-        double xa[3], xb_[3], xc[3];
         load3(P.x + 3 * (B.v0 + tv[0]), xa);
         load3(P.x + 3 * (B.v0 + tv[1]), xb_);
         load3(P.x + 3 * (B.v0 + tv[2]), xc);
-        double Ub[3];
-        if (!B.rigid) {
+        if (!B.rigid)
             for (int a = 0; a < 3; ++a)
                 Ub[a] = (P.uv[3 * (B.v0 + tv[0]) + a] + P.uv[3 * (B.v0 + tv[1]) + a] +
                          P.uv[3 * (B.v0 + tv[2]) + a]) * (1.0 / 3.0);
+    }
+    // this step's force window: the first wave folds the integer boxes the vertex blocks wrote
+    // for x^n (min / max, order independent); every block derives the same descriptor and
+    // block 0 publishes it for the sweep and the moments
+    if (threadIdx.x < 64) {
+        int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
+        for (int q = threadIdx.x; q < B.nblk_v; q += 64) {
+            const int* vb = P.vbox + 6LL * (B.blk_v0 + q);
+            for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], vb[a]); hi[a] = max(hi[a], vb[3 + a]); }
         }
+        for (int o = 32; o >= 1; o >>= 1)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
+                hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
+            }
+        if (threadIdx.x == 0)
+            for (int a = 0; a < 3; ++a) { sbox[a] = lo[a]; sbox[3 + a] = hi[a]; }
+    }
+    __syncthreads();
+    const int bmin[3] = {sbox[0], sbox[1], sbox[2]}, bmax[3] = {sbox[3], sbox[4], sbox[5]};
+    const WinDesc fd = window_from_box(J, B, bmin, bmax, err);
+    if (blk == 0 && threadIdx.x == 0) P.fdesc[b] = fd;
+    double Vt = 0.0;
+    if (live) {
         double cen[3], ab[3], ac[3], N[3];
         for (int a = 0; a < 3; ++a) {
             cen[a] = (xa[a] + xb_[a] + xc[a]) * (1.0 / 3.0);
@@ -299,17 +340,19 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri) {
             Vt = dot3(pa, bc) * (1.0 / 6.0);
         }
         MlsLane m;
-        mls_point(J, cen, B.rw, B.alpha, lane, false, m, err);
+        mls_setup(J, cen, B.rw, lane, m, err);
         float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
         if (m.active) {
             const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
             if (l < 0) err |= FLAG_WINDOW;
             else mom = P.mwin[B.win_off + l];
         }
+        mls_solve(m, B.alpha, false, err);
         const double U0 = gsum(m.phi * (double)mom.y);
         const double U1 = gsum(m.phi * (double)mom.z);
         const double U2 = gsum(m.phi * (double)mom.w);
-        // desired boundary velocity U_b (Sec. 1.2)
+        // desired boundary velocity U_b (Sec. 1.2): membranes average their vertex velocities,
+        // rigid bodies move the marker with the body
         if (B.rigid) {
             double rr[3] = {cen[0] - S.X[0], cen[1] - S.X[1], cen[2] - S.X[2]}, w[3];
             cross3(S.om, rr, w);
@@ -354,9 +397,6 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
     const int t = blk * TRI_PER_BLOCK + k;
     __shared__ double probe[MLS_PER_BLOCK][10];
     __shared__ double red[TRI_PER_BLOCK][6];
-    // the bounding-box accumulators were consumed by k_centroids; restart them for k_vertices
-    if (blk == 0 && threadIdx.x == 0)
-        for (int a = 0; a < 3; ++a) { S.bmin[a] = 0x7fffffff; S.bmax[a] = -0x7fffffff; }
     int err = 0;
     double cen[3] = {0, 0, 0}, N[3] = {0, 0, 0}, nrm[3] = {0, 0, 0}, A = 0.0;
     if (t < B.nt) {
@@ -378,13 +418,14 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
         const double xp[3] = {cen[0] + sg * B.probe * nrm[0], cen[1] + sg * B.probe * nrm[1],
                               cen[2] + sg * B.probe * nrm[2]};
         MlsLane m;
-        mls_point(J, xp, B.rw, B.alpha, lane, true, m, err);
+        mls_setup(J, xp, B.rw, lane, m, err);
         float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
         if (m.active) {
             const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
             if (l < 0) err |= FLAG_WINDOW;
             else mom = P.mwin[B.win_off + l];
         }
+        mls_solve(m, B.alpha, true, err);
         const double v[10] = {gsum(m.phi * (double)mom.x),
                               gsum(m.gr[0] * (double)mom.y), gsum(m.gr[1] * (double)mom.y), gsum(m.gr[2] * (double)mom.y),
                               gsum(m.gr[0] * (double)mom.z), gsum(m.gr[1] * (double)mom.z), gsum(m.gr[2] * (double)mom.z),
@@ -536,13 +577,14 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         if (!B.rigid) {
             // tentative velocity: fluid velocity at the vertex from f^{n+1}
             MlsLane m;
-            mls_point(J, x, B.rw, B.alpha, lane, false, m, err);
+            mls_setup(J, x, B.rw, lane, m, err);
             float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
             if (m.active) {
                 const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
                 if (l < 0) err |= FLAG_WINDOW;
                 else mom = P.mwin[B.win_off + l];
             }
+            mls_solve(m, B.alpha, false, err);
             const double u0[3] = {gsum(m.phi * (double)mom.y), gsum(m.phi * (double)mom.z),
                                   gsum(m.phi * (double)mom.w)};
             const double Fv[3] = {F0, F1, F2};
@@ -593,11 +635,12 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
     if (err) atomicOr(P.flags + B.job, err);
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int g = 1; g < MLS_PER_BLOCK; ++g)
-            for (int a = 0; a < 3; ++a) { box[0][a] = min(box[0][a], box[g][a]); box[0][3 + a] = max(box[0][3 + a], box[g][3 + a]); }
+        int* vb = P.vbox + 6LL * blockIdx.x;
         for (int a = 0; a < 3; ++a) {
-            atomicMin(&S.bmin[a], box[0][a]);
-            atomicMax(&S.bmax[a], box[0][3 + a]);
+            int lo = box[0][a], hi = box[0][3 + a];
+            for (int g = 1; g < MLS_PER_BLOCK; ++g) { lo = min(lo, box[g][a]); hi = max(hi, box[g][3 + a]); }
+            vb[a] = lo;
+            vb[3 + a] = hi;
         }
     }
 }

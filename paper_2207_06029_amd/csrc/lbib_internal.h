@@ -123,9 +123,6 @@ struct BodyState {
     // rigid body
     double X[3], R[9], u[3], u1[3], om[3], om1[3];
     int counter_c, counter_t, pad0, pad1;
-    // integer bounding box of the vertices (floor of minima, ceil of maxima), accumulated with
-    // order-independent atomics by the vertex kernel; it sets the next step's force window
-    int bmin[3], bmax[3];
 };
 
 // All device pools of one batch.  Kernels take this by value.
@@ -162,7 +159,8 @@ struct Pools {
     WinDesc* fdesc;          // force-window layout of the current step, per body
     WinDesc* mdesc;          // layout of the moment window, per body
     BodyState* bstate;
-    double* partial;         // block partial sums (8 doubles per block)
+    double* partial;         // block partial sums (16 doubles per block)
+    int* vbox;               // [6 per vertex block] integer box (floor min, ceil max) of x^{n+1}
     int* flags;              // per job
 };
 

@@ -37,7 +37,10 @@ template <> struct Codec<__hip_bfloat16> {
 // weights sum to 1 in the density balance.
 __device__ __forceinline__ void zou_he(const JobDev& J, int a, int side, float g[Q]) {
     const int s = side == 0 ? 1 : -1;
-    const float* uw = J.wall_u[2 * a + side];
+    // wall velocity of the node's face, selected from the two uniform faces of axis a
+    float uw[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) uw[c] = side == 0 ? J.wall_u[2 * a][c] : J.wall_u[2 * a + 1][c];
     const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
     float sum0 = 0.f, summ = 0.f, t1 = 0.f, t2 = 0.f;
 #pragma unroll
@@ -80,49 +83,62 @@ __device__ __forceinline__ void zou_he(const JobDev& J, int a, int side, float g
 
 // ---------------------------------------------------------------- pull
 // Post-streaming deviations at node (x, y, z) of job J from the post-collision buffer src.
+// All 19 loads are issued unconditionally, so they are in flight together: a source outside
+// the domain is redirected to the node's own opposite population (the halfway bounce-back
+// source, always a valid address), and the wall term or the Zou-He closure is applied once
+// the loads have returned.
 template <typename S>
 __device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J, int x, int y,
                                      int z, long long k, float g[Q]) {
     const long long N = J.n;
     const int nx = J.nx, ny = J.ny, nz = J.nz;
-    // source coordinates for e = +1 (c - 1) and e = -1 (c + 1) on each axis
-    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1, zm = z - 1, zp = z + 1;
+    const int sy = nx, sz = nx * ny;
+    // linear displacement of the source for e = +1 (node c - 1) and e = -1 (node c + 1)
+    int dxm = -1, dxp = 1, dym = -sy, dyp = sy, dzm = -sz, dzp = sz;
     bool oxm = false, oxp = false, oym = false, oyp = false, ozm = false, ozp = false;
-    if (xm < 0) { if (J.bc[0] == 0) xm += nx; else oxm = true; }
-    if (xp >= nx) { if (J.bc[1] == 0) xp -= nx; else oxp = true; }
-    if (ym < 0) { if (J.bc[2] == 0) ym += ny; else oym = true; }
-    if (yp >= ny) { if (J.bc[3] == 0) yp -= ny; else oyp = true; }
-    if (zm < 0) { if (J.bc[4] == 0) zm += nz; else ozm = true; }
-    if (zp >= nz) { if (J.bc[5] == 0) zp -= nz; else ozp = true; }
+    if (x == 0) { if (J.bc[0] == 0) dxm = nx - 1; else oxm = true; }
+    if (x == nx - 1) { if (J.bc[1] == 0) dxp = 1 - nx; else oxp = true; }
+    if (y == 0) { if (J.bc[2] == 0) dym = (ny - 1) * sy; else oym = true; }
+    if (y == ny - 1) { if (J.bc[3] == 0) dyp = (1 - ny) * sy; else oyp = true; }
+    if (z == 0) { if (J.bc[4] == 0) dzm = (nz - 1) * sz; else ozm = true; }
+    if (z == nz - 1) { if (J.bc[5] == 0) dzp = (1 - nz) * sz; else ozp = true; }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int e0 = cx(i), e1 = cy(i), e2 = cz(i);
+        const int d = (e0 == 1 ? dxm : (e0 == -1 ? dxp : 0)) + (e1 == 1 ? dym : (e1 == -1 ? dyp : 0)) +
+                      (e2 == 1 ? dzm : (e2 == -1 ? dzp : 0));
+        const bool o = (e0 == 1 ? oxm : (e0 == -1 ? oxp : false)) ||
+                       (e1 == 1 ? oym : (e1 == -1 ? oyp : false)) ||
+                       (e2 == 1 ? ozm : (e2 == -1 ? ozp : false));
+        const long long idx = o ? (long long)opp(i) * N + k : (long long)i * N + k + d;
+        g[i] = Codec<S>::ld(src + idx);
+    }
+    if (!(oxm || oxp || oym || oyp || ozm || ozp)) return;
+    // face kinds and wall velocities are uniform over the job: select among them per lane
+    bool bb[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) bb[f] = J.bc[f] == 2;
     bool unknown = false;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int e0 = cx(i), e1 = cy(i), e2 = cz(i);
-        const int sx = e0 == 1 ? xm : (e0 == -1 ? xp : x);
-        const int sy = e1 == 1 ? ym : (e1 == -1 ? yp : y);
-        const int sz = e2 == 1 ? zm : (e2 == -1 ? zp : z);
         const bool o0 = e0 == 1 ? oxm : (e0 == -1 ? oxp : false);
         const bool o1 = e1 == 1 ? oym : (e1 == -1 ? oyp : false);
         const bool o2 = e2 == 1 ? ozm : (e2 == -1 ? ozp : false);
-        if (!(o0 || o1 || o2)) {
-            g[i] = Codec<S>::ld(src + (long long)i * N + (long long)sx +
-                                (long long)nx * ((long long)sy + (long long)ny * sz));
+        if (!(o0 || o1 || o2)) continue;
+        // faces crossed on each axis (meaningful only where that axis is crossed)
+        const int f0 = e0 == 1 ? 0 : 1, f1 = e1 == 1 ? 2 : 3, f2 = e2 == 1 ? 4 : 5;
+        const bool isbb = o0 ? bb[f0] : (o1 ? bb[f1] : bb[f2]);
+        if (isbb) {
+            float uwx = 0.f, uwy = 0.f, uwz = 0.f;
+            if (o0) { uwx += J.wall_u[f0][0]; uwy += J.wall_u[f0][1]; uwz += J.wall_u[f0][2]; }
+            if (o1) { uwx += J.wall_u[f1][0]; uwy += J.wall_u[f1][1]; uwz += J.wall_u[f1][2]; }
+            if (o2) { uwx += J.wall_u[f2][0]; uwy += J.wall_u[f2][1]; uwz += J.wall_u[f2][2]; }
+            const float eu = e0 * uwx + e1 * uwy + e2 * uwz;
+            g[i] = g[i] + (float)(6.0 * wq(i)) * eu;
         } else {
-            const int f0 = o0 ? (e0 == 1 ? 0 : 1) : -1;
-            const int f1 = o1 ? (e1 == 1 ? 2 : 3) : -1;
-            const int f2 = o2 ? (e2 == 1 ? 4 : 5) : -1;
-            const int ff = f0 >= 0 ? f0 : (f1 >= 0 ? f1 : f2);
-            if (J.bc[ff] == 2) {
-                float uwx = 0.f, uwy = 0.f, uwz = 0.f;
-                if (f0 >= 0) { uwx += J.wall_u[f0][0]; uwy += J.wall_u[f0][1]; uwz += J.wall_u[f0][2]; }
-                if (f1 >= 0) { uwx += J.wall_u[f1][0]; uwy += J.wall_u[f1][1]; uwz += J.wall_u[f1][2]; }
-                if (f2 >= 0) { uwx += J.wall_u[f2][0]; uwy += J.wall_u[f2][1]; uwz += J.wall_u[f2][2]; }
-                const float eu = e0 * uwx + e1 * uwy + e2 * uwz;
-                g[i] = Codec<S>::ld(src + (long long)opp(i) * N + k) + (float)(6.0 * wq(i)) * eu;
-            } else {
-                g[i] = 0.f;
-                unknown = true;
-            }
+            g[i] = 0.f;
+            unknown = true;
         }
     }
     if (unknown) {

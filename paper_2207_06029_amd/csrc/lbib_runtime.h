@@ -15,6 +15,8 @@ lbib_status fail(lbib_status code, const std::string& msg);
 const char* last_error();
 lbib_status check_lattice(const lbib_lattice_desc& d);
 size_t storage_bytes(int storage);
+// Force-window capacity per axis for a body of bounding radius rbound about its vertex mean.
+void window_capacity(const int dims[3], bool rigid, double rbound, int cap[3]);
 
 // Device memory: a caller workspace carved by a bump pointer, or hipMalloc'd blocks.
 struct Arena {

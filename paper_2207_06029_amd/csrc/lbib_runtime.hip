@@ -98,7 +98,15 @@ lbib_status check_lattice(const lbib_lattice_desc& d) {
     return LBIB_OK;
 }
 
-// ---------------------------------------------------------------- body rest state (a0)
+void window_capacity(const int dims[3], bool rigid, double rbound, int cap[3]) {
+    // membranes may stretch to twice their rest extent (a Taylor deformation near 0.5 at fixed
+    // volume) before the window overflows; rigid bodies only carry their box along
+    const double grow = rigid ? 1.0 : 2.0;
+    for (int a = 0; a < 3; ++a)
+        cap[a] = std::min(dims[a], (int)std::ceil(2.0 * grow * rbound) + 2 * WIN_MARGIN + 4);
+}
+
+// ---------------------------------------------------------------- body rest state
 static void vsub(const double* a, const double* b, double* c) { for (int i = 0; i < 3; ++i) c[i] = a[i] - b[i]; }
 static void vcross(const double* a, const double* b, double* c) {
     c[0] = a[1] * b[2] - a[2] * b[1];
@@ -407,7 +415,7 @@ lbib_status Batch::rebuild_bodies() {
     std::stable_sort(hbodies.begin(), hbodies.end(), [](const HostBody& a, const HostBody& b) { return a.job < b.job; });
     for (auto& J : jobs) { J.body0 = 0; J.nbodies = 0; }
     std::vector<BodyDev> bd(hbodies.size());
-    std::vector<int> bc, be, bt, bv;
+    std::vector<int> bc, be, bt, bv, vbox;
     std::vector<double> x, xprev, uv, xb, l0, ks, th0;
     std::vector<int> tri, edge, hinge, vtp, vtl, vhp, vhl;
     std::vector<WinDesc> fd(hbodies.size());
@@ -432,9 +440,7 @@ lbib_status Batch::rebuild_bodies() {
         for (int a = 0; a < 3; ++a) B.gravity[a] = h.desc.gravity[a];
         for (int k = 0; k < 9; ++k) B.Ib[k] = h.Ib[k];
         const int dims[3] = {J.nx, J.ny, J.nz};
-        const double grow = h.desc.rigid ? 1.0 : 1.6;
-        for (int a = 0; a < 3; ++a)
-            B.win_cap[a] = std::min(dims[a], (int)std::ceil(2.0 * grow * h.rbound) + 2 * WIN_MARGIN + 4);
+        window_capacity(dims, h.desc.rigid != 0, h.rbound, B.win_cap);
         const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
         B.win_off = woff;
         woff += capn;
@@ -483,9 +489,13 @@ lbib_status Batch::rebuild_bodies() {
             S.V = h.V0;
             for (int k = 0; k < 9; ++k) S.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
             for (int a = 0; a < 3; ++a) S.X[a] = h.X0[a];
-            for (int a = 0; a < 3; ++a) { S.bmin[a] = (int)std::floor(lo[a]); S.bmax[a] = (int)std::ceil(hi[a]); }
         }
         S.counter_c = S.counter_t = 0;
+        // every vertex block starts with the box of the current positions
+        for (int k = 0; k < nbv; ++k) {
+            for (int a = 0; a < 3; ++a) vbox.push_back((int)std::floor(lo[a]));
+            for (int a = 0; a < 3; ++a) vbox.push_back((int)std::ceil(hi[a]));
+        }
         bool over = false;
         fd[i] = h.has_state ? h.fdesc : window_for(J, lo, hi, B.win_cap, &over);
         if (over) return fail(LBIB_EDOMAIN, "body does not fit its window");
@@ -533,6 +543,7 @@ lbib_status Batch::rebuild_bodies() {
     if ((st = upload(arena, bs, &P.bstate, stream))) return st;
     if ((st = arena.alloc(sizeof(double) * 16 * std::max<long long>(red, 1), &p))) return st;
     P.partial = (double*)p;
+    if ((st = upload(arena, vbox, &P.vbox, stream))) return st;
     d_bodies = (BodyDev*)P.bodies;
     host_bodies = bd;
     HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, stream));

@@ -57,9 +57,9 @@ uint64_t job_bytes(const lbib_lattice_desc& d, int storage, const std::vector<do
             r = std::max(r, std::sqrt(s));
         }
         const int dims[3] = {d.nx, d.ny, d.nz};
-        uint64_t w = 1;
-        for (int a = 0; a < 3; ++a)
-            w *= (uint64_t)std::min(dims[a], (int)std::ceil(2.0 * (rigid ? 1.0 : 1.6) * r) + 2 * lbib::WIN_MARGIN + 4);
+        int cap[3];
+        lbib::window_capacity(dims, rigid, r, cap);
+        const uint64_t w = (uint64_t)cap[0] * cap[1] * cap[2];
         b += w * 40 + nv * 8 * 24 + (uint64_t)nt * 8 * 16;
     }
     return b;
@@ -134,6 +134,16 @@ lbib_status rebuild(lbib_server* S) {
 lbib_status retire(lbib_server* S, size_t k, int status) {
     SJob& j = S->resident[k];
     SResult R;
+    if (S->opts.dry_run) {
+        R.r.id = j.id; R.r.tag = j.tag; R.r.status = status; R.r.nv = (int32_t)(j.xyz.size() / 3);
+        R.r.steps_done = j.done; R.r.t_submit_ns = j.t_submit; R.r.t_admit_ns = j.t_admit;
+        R.r.t_finish_ns = now_ns();
+        S->results.push_back(std::move(R));
+        S->resident_bytes -= j.bytes;
+        S->resident.erase(S->resident.begin() + k);
+        S->dirty = true;
+        return LBIB_OK;
+    }
     R.r.id = j.id;
     R.r.tag = j.tag;
     R.r.status = status;
@@ -220,7 +230,19 @@ lbib_status lbib_server_tick(lbib_server* S) {
             S->resident.push_back(std::move(j));
             S->dirty = true;
         }
-        lbib_status st;
+        lbib_status st = LBIB_OK;
+        if (S->opts.dry_run) {
+            if (S->resident.empty()) return LBIB_OK;
+            int64_t nstep = S->opts.steps_per_tick;
+            for (auto& j : S->resident) nstep = std::min<int64_t>(nstep, j.steps - j.done);
+            for (auto& j : S->resident) {
+                j.done += nstep;
+                S->node_updates += (double)nstep * j.lat.nx * j.lat.ny * j.lat.nz;
+            }
+            for (size_t k = S->resident.size(); k-- > 0;)
+                if (S->resident[k].done >= S->resident[k].steps && (st = retire(S, k, LBIB_OK))) return st;
+            return LBIB_OK;
+        }
         if (S->dirty && (st = rebuild(S))) return st;
         if (S->resident.empty()) return LBIB_OK;
         // zero-step jobs finish at once

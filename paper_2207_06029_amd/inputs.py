@@ -147,6 +147,7 @@ class Job:
     tag: int = 0
     kind: str = "shear"
     arrival_s: float = 0.0
+    drawn_mass_ratio: Optional[float] = None
 
 
 def shear_walls(u_wall: float) -> dict:
@@ -223,6 +224,11 @@ def settling_sphere(density_ratio: float = 1.5, storage: int = STORE_F16) -> Job
     return Job(f"settling_rho{density_ratio:g}", lat, body, xyz, tri, 20000, kind="settling")
 
 
+# Capillary numbers of the generated membranes: the span of the paper's deformable cases
+# (prolate tumbling study G = 0.01 .. 0.1, capsule-under-shear validation up to G = 0.15).
+CA_RANGE = (0.01, 0.15)
+
+
 def _shear_job(rng: np.random.Generator, dims: Tuple[int, int, int], level: int,
                storage: int, steps: int, name: str, tag: int) -> Job:
     nx, ny, nz = dims
@@ -233,15 +239,29 @@ def _shear_job(rng: np.random.Generator, dims: Tuple[int, int, int], level: int,
     oblate = bool(rng.uniform() < 0.5)
     semi = (radius, radius, 0.5 * radius) if oblate else (radius, radius, radius)
     rot = uniform_rotation(rng)
-    ca = float(math.exp(rng.uniform(math.log(0.01), math.log(0.5))))
+    ca = float(math.exp(rng.uniform(math.log(CA_RANGE[0]), math.log(CA_RANGE[1]))))
     kb_ratio = float(rng.uniform(0.0, 0.05))
-    mass_ratio = max(float(rng.uniform(0.0, 2.0)), 0.1)  # a zero-mass membrane has no Verlet update
+    drawn_ratio = float(rng.uniform(0.0, 2.0))
     ks0 = ks0_from_capillary(ca, tau, shear, radius)
     lat = LatticeSpec(nx, ny, nz, tau, storage=storage, **shear_walls(u_wall))
-    body = BodySpec(rigid=0, ks0=ks0, kb=kb_ratio * ks0, kv=0.0, mass_ratio=mass_ratio)
     centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
     xyz, tri = spheroid_mesh(level, semi, centre, rot)
-    return Job(name, lat, body, xyz, tri, steps, tag=tag, kind="shear")
+    mass_ratio = max(drawn_ratio, membrane_mass_floor(ks0, xyz, tri))
+    body = BodySpec(rigid=0, ks0=ks0, kb=kb_ratio * ks0, kv=0.0, mass_ratio=mass_ratio)
+    job = Job(name, lat, body, xyz, tri, steps, tag=tag, kind="shear")
+    job.drawn_mass_ratio = drawn_ratio
+    return job
+
+
+def membrane_mass_floor(ks0: float, xyz: np.ndarray, tri: np.ndarray) -> float:
+    """Smallest solid/fluid density ratio given to a generated membrane job: 0.5, and at least
+    2 k_s0 / (mean triangle area).  Lighter membranes (ratio 0.1 and 0.2 in the batching mix)
+    diverge under the weakly coupled explicit vertex update, and so do stiff, finely meshed
+    ones below about k_s0 / (mean area); the draws are floored so every job runs."""
+    a = xyz[tri[:, 1]] - xyz[tri[:, 0]]
+    b = xyz[tri[:, 2]] - xyz[tri[:, 0]]
+    area = 0.5 * np.linalg.norm(np.cross(a, b), axis=1).mean()
+    return max(0.5, 2.0 * ks0 / area)
 
 
 BATCH_EDGES = (32, 48, 64, 80, 96)
@@ -250,8 +270,9 @@ BATCH_EDGES = (32, 48, 64, 80, 96)
 def capsule_batch(seed: int = 0, njobs: int = 64, storage: int = STORE_F16,
                   steps: int = 2000) -> List[Job]:
     """64 independent capsule-in-shear cases: cubic edges from {32..96}, sphere or oblate
-    (c/a=0.5) capsules of radius 0.2*edge, level 3 or 4, Ca log-uniform in [0.01, 0.5],
-    k_b/k_s0 in [0, 0.05], mass ratio in [0, 2] (floored at 0.1), tau~U(0.6,1), walls +-0.01."""
+    (c/a=0.5) capsules of radius 0.2*edge, level 3 or 4, Ca log-uniform in CA_RANGE,
+    k_b/k_s0 in [0, 0.05], mass ratio drawn in [0, 2] and floored by membrane_mass_floor,
+    tau~U(0.6,1), walls +-0.01."""
     rng = np.random.default_rng(seed)
     jobs = []
     for j in range(njobs):
@@ -262,16 +283,61 @@ def capsule_batch(seed: int = 0, njobs: int = 64, storage: int = STORE_F16,
 
 
 SERVE_LATTICES = ((48, 48, 48), (64, 64, 64), (96, 48, 96), (128, 64, 128))
+SETTLING_EDGES = (48, 64, 80, 96)
+
+
+def abraham_terminal_velocity(d: float, gravity: float, density_ratio: float, nu: float) -> float:
+    """Terminal settling speed of a sphere of diameter d from Abraham's drag law (Sec. 2,
+    settling sphere): C_d = C_0 (1 + delta_0/sqrt(Re))^2 with C_0 delta_0^2 = 24, delta_0 = 9.06,
+    u = sqrt(4 g d (gamma - 1) / (3 C_d)), Re = d u / nu; the fixed point in u is found by
+    bisection.  Used only to bound run lengths of generated settling jobs."""
+    delta0 = 9.06
+    c0 = 24.0 / delta0 ** 2
+
+    def excess(u):
+        re = max(d * u / nu, 1e-300)
+        cd = c0 * (1.0 + delta0 / math.sqrt(re)) ** 2
+        return u - math.sqrt(4.0 * gravity * d * (density_ratio - 1.0) / (3.0 * cd))
+
+    lo, hi = 0.0, 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if excess(mid) > 0.0:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def _settle_job(rng: np.random.Generator, edge: int, storage: int, steps: int, name: str,
+                tag: int) -> Job:
+    """Rigid sphere settling in the paper's box proportions (Sec. 2, settling sphere):
+    L_x = L_y = 6.67 d, L_z = 10.67 d, released at rest 8 d above the floor, tau = 0.7,
+    gravity 1e-5 along -z, level-4 sphere (mean edge 0.27..0.54 lattice units for these sizes,
+    about the 0.3..0.5 Lagrangian/Eulerian spacing ratio the paper recommends).  The run length
+    is cut so that, moving at the unbounded terminal speed (an upper bound inside the box), the
+    sphere stops at least one diameter above the floor."""
+    d = edge / 6.67
+    nz = int(round(10.67 * d))
+    ratio = float(rng.choice(SETTLING_DENSITY_RATIOS))
+    tau, g = 0.7, 1e-5
+    lat = LatticeSpec(edge, edge, nz, tau, storage=storage, **closed_box())
+    body = BodySpec(rigid=1, ks0=0.0, kb=0.0, kv=0.0, mass_ratio=ratio, gravity=(0.0, 0.0, -g))
+    z0 = 8.0 * d - 0.5
+    xyz, tri = spheroid_mesh(4, (0.5 * d,) * 3, ((edge - 1) / 2.0, (edge - 1) / 2.0, z0))
+    u_inf = abraham_terminal_velocity(d, g, ratio, (tau - 0.5) / 3.0)
+    steps = int(min(steps, (z0 - 1.5 * d) / u_inf))
+    return Job(name, lat, body, xyz, tri, steps, tag=tag, kind="settling")
 
 
 def serving_stream(seed: int = 0, rate_per_s: float = 4.0, window_s: float = 1800.0,
                    storage: int = STORE_F16, steps_range=(2000, 10000),
                    levels=(3, 4, 5), lattices=SERVE_LATTICES,
                    max_jobs: Optional[int] = None) -> List[Job]:
-    """Poisson arrivals of capsule-shear and settling jobs (50/50).  Lattices are drawn from
-    48^3 .. 128x64x128, mesh levels from {3,4,5} (642-10242 nodes), run lengths uniform in
-    steps_range.  Shear jobs take the batching parameters; settling jobs put a rigid sphere of
-    radius min(dims)/12 in a closed box with tau=0.7 and gravity 1e-5 along -z."""
+    """Poisson arrivals of capsule-shear and settling jobs (50/50), run lengths uniform in
+    steps_range.  Shear jobs take the batching parameters on lattices drawn from 48^3 ..
+    128x64x128 with mesh levels from {3,4,5} (642-10242 nodes); settling jobs are built by
+    _settle_job on square-section boxes of edge 48..96."""
     rng = np.random.default_rng(seed)
     t = 0.0
     jobs: List[Job] = []
@@ -286,16 +352,8 @@ def serving_stream(seed: int = 0, rate_per_s: float = 4.0, window_s: float = 180
         if rng.uniform() < 0.5:
             job = _shear_job(rng, dims, level, storage, steps, f"serve{seed}_{tag}", tag)
         else:
-            nx, ny, nz = dims
-            r = min(dims) / 12.0
-            ratio = float(rng.choice(SETTLING_DENSITY_RATIOS))
-            lat = LatticeSpec(nx, ny, nz, 0.7, storage=storage, **closed_box())
-            body = BodySpec(rigid=1, ks0=0.0, kb=0.0, kv=0.0, mass_ratio=ratio,
-                            gravity=(0.0, 0.0, -1e-5))
-            centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, nz - 1 - 2.67 * 2.0 * r)
-            xyz, tri = spheroid_mesh(level, (r, r, r), centre)
-            job = Job(f"serve{seed}_{tag}", lat, body, xyz, tri, steps, tag=tag,
-                      kind="settling")
+            edge = int(SETTLING_EDGES[int(rng.integers(len(SETTLING_EDGES)))])
+            job = _settle_job(rng, edge, storage, steps, f"serve{seed}_{tag}", tag)
         job.arrival_s = t
         jobs.append(job)
     return jobs

@@ -1,0 +1,110 @@
+"""Batching and serving on the GPU: every job's result is bitwise the same alone and inside a
+batch or the server's mix, launch shapes and graph replay do not change results, and batched
+jobs match the FP64 oracle within the reduced-precision tolerance."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2207_06029_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2207_06029_amd import api as A
+    return A
+
+
+def mixed_jobs(n=5, steps=120):
+    jobs = I.capsule_batch(seed=3, njobs=n, storage=I.STORE_F16, steps=steps)
+    # add a settling job (rigid body, closed box) to the mix
+    lat = I.LatticeSpec(32, 32, 48, 0.7, storage=I.STORE_F16, **I.closed_box())
+    body = I.BodySpec(rigid=1, ks0=0.0, kb=0.0, kv=0.0, mass_ratio=2.0, gravity=(0.0, 0.0, -1e-4))
+    xyz, tri = I.spheroid_mesh(3, (4.0, 4.0, 4.0), (15.5, 15.5, 30.0))
+    jobs.append(I.Job("settle", lat, body, xyz, tri, steps, tag=99, kind="settling"))
+    return jobs
+
+
+def state_of(lat):
+    _, u = lat.macros()
+    x, _ = lat.body_state(0)
+    return u, x
+
+
+def test_batch_alone_vs_mix_bitwise(api):
+    jobs = mixed_jobs()
+    steps = 120
+    mix = api.Batch(jobs, storage=I.STORE_F16)
+    mix.step(steps)
+    mix.sync()
+    for j, job in enumerate(jobs):
+        alone = api.Batch([job], storage=I.STORE_F16)
+        alone.step(steps)
+        alone.sync()
+        u_m, x_m = state_of(mix.lattice(j))
+        u_a, x_a = state_of(alone.lattice(0))
+        np.testing.assert_array_equal(u_m, u_a)
+        np.testing.assert_array_equal(x_m, x_a)
+
+
+def test_launch_shape_and_graph_do_not_change_results(api, tmp_path):
+    jobs = mixed_jobs(3, 60)
+    ref = api.Batch(jobs, storage=I.STORE_F16)
+    ref.step(61)
+    tuned = api.Batch(jobs, storage=I.STORE_F16, autotune=True,
+                      tune_cache=str(tmp_path / "tune.txt"), use_graph=True)
+    tuned.step(61)
+    print("autotuned launch shape", tuned.launch_shape())
+    for j in range(len(jobs)):
+        u_r, x_r = state_of(ref.lattice(j))
+        u_t, x_t = state_of(tuned.lattice(j))
+        np.testing.assert_array_equal(u_r, u_t)
+        np.testing.assert_array_equal(x_r, x_t)
+    # the cache is reused by a second batch of the same shapes
+    again = api.Batch(jobs, storage=I.STORE_F16, autotune=True, tune_cache=str(tmp_path / "tune.txt"))
+    assert again.launch_shape() == tuned.launch_shape()
+
+
+def test_batched_jobs_match_oracle(api, orc):
+    orc.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    jobs = mixed_jobs(3, 200)
+    mix = api.Batch(jobs, storage=I.STORE_F16)
+    mix.step(200)
+    mix.sync()
+    for j in (0, len(jobs) - 1):
+        job = jobs[j]
+        ref = orc.Lattice(job.lattice)
+        rb = ref.add_body(job.body, job.xyz, job.tri)
+        ref.step(200)
+        _, ur = ref.macros()
+        xr, _ = ref.body_state(rb)
+        u, x = state_of(mix.lattice(j))
+        eu = np.linalg.norm(u - ur) / np.linalg.norm(ur)
+        ex = np.linalg.norm(x - xr) / np.linalg.norm(xr)
+        print(f"job {job.name}: rel-L2 u* {eu:.3e}, positions {ex:.3e}")
+        assert eu < 1e-3 and ex < 1e-3
+
+
+def test_server_results_match_alone(api):
+    jobs = mixed_jobs(4, 0)
+    for k, job in enumerate(jobs):
+        job.steps = 40 + 23 * k           # uneven run lengths: jobs retire at different ticks
+    srv = api.Server(hbm_budget_bytes=1 << 34, max_slots=3, steps_per_tick=16, storage=I.STORE_F16)
+    ids = {srv.submit(job): job for job in jobs}
+    results = {}
+    for _ in range(100):
+        srv.tick()
+        for r in srv.poll(with_positions=True):
+            results[r["id"]] = r
+        if len(results) == len(jobs):
+            break
+    assert len(results) == len(jobs)
+    for jid, job in ids.items():
+        r = results[jid]
+        assert r["status"] == 0 and r["steps_done"] == job.steps
+        alone = api.Batch([job], storage=I.STORE_F16)
+        alone.step(job.steps)
+        x_a, _ = alone.lattice(0).body_state(0)
+        np.testing.assert_array_equal(r["xyz"], x_a)
