@@ -26,6 +26,27 @@ if ROOT not in sys.path:
 METRIC = "fused D3Q19+IB MLUPS & HBM-roofline %; batched jobs/h, p50/p99 latency"
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the FP32 sweep on the 128x64x128 case, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counters scaled by a plain copy of known size (fetch x2.0, write x1.0).  Reported
+# only while the sweep's sources hash to the value they had when the counters were taken.
+SWEEP_SOURCES = ("paper_2207_06029_amd/csrc/lbib_lattice.hip", "paper_2207_06029_amd/csrc/lbib_internal.h")
+SWEEP_TRAFFIC = {"sha256": None, "bytes": None}
+
+
+def sources_sha256(paths=SWEEP_SOURCES) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    if SWEEP_TRAFFIC["sha256"] and SWEEP_TRAFFIC["sha256"] == sources_sha256():
+        return SWEEP_TRAFFIC["bytes"]
+    return None
+
 
 def cpu_baseline(job, target_s: float = 15.0) -> dict:
     """The FP64 oracle (as it stands) on the same workload, timed on the host's cores."""
@@ -37,7 +58,7 @@ def cpu_baseline(job, target_s: float = 15.0) -> dict:
     t0 = time.perf_counter()
     lat.step(1)
     one = time.perf_counter() - t0
-    n = max(1, min(200, int(target_s / max(one, 1e-3))))
+    n = max(1, min(5000, int(target_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     lat.step(n)
     dt = time.perf_counter() - t0
@@ -49,16 +70,23 @@ def cpu_baseline(job, target_s: float = 15.0) -> dict:
 
 
 def calibrate_copy(nbytes: int, reps: int) -> None:
-    """Plain device copies of known size, for scaling the HBM byte counters."""
+    """Plain device copies of known size: the reference for scaling the HBM byte counters, and
+    the read+write bandwidth a streaming kernel can reach (timed with HIP events)."""
     import torch
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
+    b.copy_(a)
     torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
     for _ in range(reps):
         b.copy_(a)
+    t1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"calibration_copy_bytes": nbytes, "reps": reps}))
+    us = t0.elapsed_time(t1) * 1e3 / reps
+    print(json.dumps({"calibration_copy_bytes": nbytes, "reps": reps, "avg_us": round(us, 3),
+                      "read_plus_write_GBs": round(2 * nbytes / us / 1e3, 1)}))
 
 
 def bench_batch(args) -> dict:
@@ -206,7 +234,12 @@ def main() -> int:
                     help="also time the same steps replayed from a captured hipGraph")
     ap.add_argument("--mode", choices=["plain", "batch", "serve"], default="plain")
     ap.add_argument("--serve-window", type=float, default=60.0)
+    ap.add_argument("--sources-sha256", action="store_true",
+                    help="print the hash of the sweep's sources and exit")
     args = ap.parse_args()
+    if args.sources_sha256:
+        print(sources_sha256())
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not part of this build", file=sys.stderr)
@@ -269,7 +302,7 @@ def main() -> int:
                    "lattice": [spec.nx, spec.ny, spec.nz], "markers": int(len(job.tri)),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_sweep<float,collide>",
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": round(sweep_avg_s * 1e6, 3)},

@@ -171,8 +171,10 @@ struct SweepShape {
 };
 
 // lbib_lattice.hip
+// With ev0/ev1 set, the two events are stamped by the sweep's own dispatch packet (its start
+// and end on the device), not by separate stream commands around it.
 void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int ntiles,
-                  SweepShape shape, hipStream_t s);
+                  SweepShape shape, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_window_moments(const Pools& P, int storage, bool from_b, int nbodies, int max_cap,
                            hipStream_t s);
 void launch_macros(const Pools& P, int storage, bool from_b, int job, long long n, float* out4,

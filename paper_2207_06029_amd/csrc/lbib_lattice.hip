@@ -8,6 +8,8 @@
 // (sweep, moments, getters) uses the same pull, so the post-streaming state is never stored.
 #include "lbib_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace lbib {
 
 // ---------------------------------------------------------------- storage codecs
@@ -244,25 +246,35 @@ __global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b) {
     }
 }
 
+template <typename S, bool C, int NPT>
+static void sweep_n(const Pools& P, bool a_to_b, dim3 grid, dim3 block, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1) {
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL((k_sweep<S, C, NPT>), grid, block, 0, s, ev0, ev1, 0, P, (int)a_to_b);
+    else
+        hipLaunchKernelGGL((k_sweep<S, C, NPT>), grid, block, 0, s, P, (int)a_to_b);
+}
+
 template <typename S, bool C>
-static void sweep_t(const Pools& P, bool a_to_b, int ntiles, SweepShape sh, hipStream_t s) {
+static void sweep_t(const Pools& P, bool a_to_b, int ntiles, SweepShape sh, hipStream_t s,
+                    hipEvent_t ev0, hipEvent_t ev1) {
     dim3 grid(ntiles), block(sh.block);
     switch (sh.npt) {
-        case 1: hipLaunchKernelGGL((k_sweep<S, C, 1>), grid, block, 0, s, P, (int)a_to_b); break;
-        case 2: hipLaunchKernelGGL((k_sweep<S, C, 2>), grid, block, 0, s, P, (int)a_to_b); break;
-        default: hipLaunchKernelGGL((k_sweep<S, C, 4>), grid, block, 0, s, P, (int)a_to_b); break;
+        case 1: sweep_n<S, C, 1>(P, a_to_b, grid, block, s, ev0, ev1); break;
+        case 2: sweep_n<S, C, 2>(P, a_to_b, grid, block, s, ev0, ev1); break;
+        default: sweep_n<S, C, 4>(P, a_to_b, grid, block, s, ev0, ev1); break;
     }
 }
 
 void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int ntiles,
-                  SweepShape shape, hipStream_t s) {
+                  SweepShape shape, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ntiles <= 0) return;
-    if (storage == 0) collide ? sweep_t<float, true>(P, a_to_b, ntiles, shape, s)
-                              : sweep_t<float, false>(P, a_to_b, ntiles, shape, s);
-    else if (storage == 1) collide ? sweep_t<__half, true>(P, a_to_b, ntiles, shape, s)
-                                   : sweep_t<__half, false>(P, a_to_b, ntiles, shape, s);
-    else collide ? sweep_t<__hip_bfloat16, true>(P, a_to_b, ntiles, shape, s)
-                 : sweep_t<__hip_bfloat16, false>(P, a_to_b, ntiles, shape, s);
+    if (storage == 0) collide ? sweep_t<float, true>(P, a_to_b, ntiles, shape, s, ev0, ev1)
+                              : sweep_t<float, false>(P, a_to_b, ntiles, shape, s, ev0, ev1);
+    else if (storage == 1) collide ? sweep_t<__half, true>(P, a_to_b, ntiles, shape, s, ev0, ev1)
+                                   : sweep_t<__half, false>(P, a_to_b, ntiles, shape, s, ev0, ev1);
+    else collide ? sweep_t<__hip_bfloat16, true>(P, a_to_b, ntiles, shape, s, ev0, ev1)
+                 : sweep_t<__hip_bfloat16, false>(P, a_to_b, ntiles, shape, s, ev0, ev1);
 }
 
 // ---------------------------------------------------------------- window moments

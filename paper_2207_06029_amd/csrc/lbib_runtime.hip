@@ -99,9 +99,10 @@ lbib_status check_lattice(const lbib_lattice_desc& d) {
 }
 
 void window_capacity(const int dims[3], bool rigid, double rbound, int cap[3]) {
-    // membranes may stretch to twice their rest extent (a Taylor deformation near 0.5 at fixed
-    // volume) before the window overflows; rigid bodies only carry their box along
-    const double grow = rigid ? 1.0 : 2.0;
+    // membranes may stretch to 2.5 times their rest extent (a Taylor deformation near 0.6 at
+    // fixed volume) before the window overflows; rigid bodies only carry their box along.  Only
+    // memory scales with the capacity: kernels cover the current window.
+    const double grow = rigid ? 1.0 : 2.5;
     for (int a = 0; a < 3; ++a)
         cap[a] = std::min(dims[a], (int)std::ceil(2.0 * grow * rbound) + 2 * WIN_MARGIN + 4);
 }
@@ -702,9 +703,7 @@ lbib_status Batch::enqueue_step(bool collide) {
         lbib_status st = next_event(&a);
         if (!st) st = next_event(&b);
         if (st) return st;
-        HIP_TRY(hipEventRecord(a, stream));
-        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, stream);
-        HIP_TRY(hipEventRecord(b, stream));
+        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, stream, a, b);
         sweep_events.push_back({a, b});
     } else {
         launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, stream);

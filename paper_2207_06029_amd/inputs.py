@@ -224,9 +224,9 @@ def settling_sphere(density_ratio: float = 1.5, storage: int = STORE_F16) -> Job
     return Job(f"settling_rho{density_ratio:g}", lat, body, xyz, tri, 20000, kind="settling")
 
 
-# Capillary numbers of the generated membranes: the span of the paper's deformable cases
-# (prolate tumbling study G = 0.01 .. 0.1, capsule-under-shear validation up to G = 0.15).
-CA_RANGE = (0.01, 0.15)
+# Capillary numbers of the generated membranes, log-uniform: from the stiffest of the paper's
+# deformable cases (G = 0.01, prolate tumbling study) to strongly deforming capsules (0.5).
+CA_RANGE = (0.01, 0.5)
 
 
 def _shear_job(rng: np.random.Generator, dims: Tuple[int, int, int], level: int,
@@ -283,7 +283,7 @@ def capsule_batch(seed: int = 0, njobs: int = 64, storage: int = STORE_F16,
 
 
 SERVE_LATTICES = ((48, 48, 48), (64, 64, 64), (96, 48, 96), (128, 64, 128))
-SETTLING_EDGES = (48, 64, 80, 96)
+SETTLING_EDGES = (48, 64, 80)
 
 
 def abraham_terminal_velocity(d: float, gravity: float, density_ratio: float, nu: float) -> float:
@@ -313,7 +313,7 @@ def _settle_job(rng: np.random.Generator, edge: int, storage: int, steps: int, n
                 tag: int) -> Job:
     """Rigid sphere settling in the paper's box proportions (Sec. 2, settling sphere):
     L_x = L_y = 6.67 d, L_z = 10.67 d, released at rest 8 d above the floor, tau = 0.7,
-    gravity 1e-5 along -z, level-4 sphere (mean edge 0.27..0.54 lattice units for these sizes,
+    gravity 1e-5 along -z, level-4 sphere (mean edge 0.27..0.45 lattice units for these sizes,
     about the 0.3..0.5 Lagrangian/Eulerian spacing ratio the paper recommends).  The run length
     is cut so that, moving at the unbounded terminal speed (an upper bound inside the box), the
     sphere stops at least one diameter above the floor."""
@@ -337,7 +337,7 @@ def serving_stream(seed: int = 0, rate_per_s: float = 4.0, window_s: float = 180
     """Poisson arrivals of capsule-shear and settling jobs (50/50), run lengths uniform in
     steps_range.  Shear jobs take the batching parameters on lattices drawn from 48^3 ..
     128x64x128 with mesh levels from {3,4,5} (642-10242 nodes); settling jobs are built by
-    _settle_job on square-section boxes of edge 48..96."""
+    _settle_job on square-section boxes of edge 48..80 (at most 80x80x128 nodes)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     jobs: List[Job] = []
