@@ -6,8 +6,11 @@ seed 0, walls at shear rate 1e-4, prolate spheroid a=12, b=c=6, level-4 mesh (25
 5120 markers), Ca=0.05, k_b = 0.01 k_s0, FP32 shifted populations.  One step = MLS forcing and
 spreading, the fused collide+stream sweep, window moments, probe stresses and the membrane
 update (all HIP kernels of the library).  value = lattice node updates per second (MLUPS) over
-the timed steps.  The sweep's average launch duration comes from HIP events recorded around
-every sweep launch on the lattice's stream inside the timed region.
+the timed steps.  The sweep's average launch duration comes from start/end events stamped by
+every sweep launch's own dispatch packet on the lattice's stream inside the timed region.
+`--workload prolate256` runs the same physics at 256x128x256 (level-5 mesh), a working set
+larger than the Infinity Cache.  `--mode batch` and `--mode serve` run the batched and served
+forms (64 capsule jobs; a Poisson stream of capsule and settling jobs).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
@@ -30,7 +33,10 @@ PEAK_HBM_GBS = 8000.0
 # WRITE_SIZE counters scaled by a plain copy of known size (fetch x2.0, write x1.0).  Reported
 # only while the sweep's sources hash to the value they had when the counters were taken.
 SWEEP_SOURCES = ("paper_2207_06029_amd/csrc/lbib_lattice.hip", "paper_2207_06029_amd/csrc/lbib_internal.h")
-SWEEP_TRAFFIC = {"sha256": None, "bytes": None}
+SWEEP_TRAFFIC = {
+    "prolate128": {"sha256": None, "bytes": None},
+    "prolate256": {"sha256": None, "bytes": None},
+}
 
 
 def sources_sha256(paths=SWEEP_SOURCES) -> str:
@@ -42,10 +48,20 @@ def sources_sha256(paths=SWEEP_SOURCES) -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    if SWEEP_TRAFFIC["sha256"] and SWEEP_TRAFFIC["sha256"] == sources_sha256():
-        return SWEEP_TRAFFIC["bytes"]
+def measured_traffic(workload: str):
+    rec = SWEEP_TRAFFIC.get(workload, {})
+    if rec.get("sha256") and rec["sha256"] == sources_sha256():
+        return rec["bytes"]
     return None
+
+
+# Plain FP32 workloads: the prolate capsule in shear at 128x64x128 (the headline case) and the
+# same physics at twice the linear size, whose populations (2 x 637 MB) do not fit the 256 MB
+# Infinity Cache.
+WORKLOADS = {
+    "prolate128": ("prolate_shear", "level-4 mesh (2562 vertices, 5120 markers)"),
+    "prolate256": ("prolate_shear_large", "level-5 mesh (10242 vertices, 20480 markers)"),
+}
 
 
 def cpu_baseline(job, target_s: float = 15.0) -> dict:
@@ -233,6 +249,8 @@ def main() -> int:
     ap.add_argument("--graph", action="store_true",
                     help="also time the same steps replayed from a captured hipGraph")
     ap.add_argument("--mode", choices=["plain", "batch", "serve"], default="plain")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="prolate128",
+                    help="plain mode: 128x64x128 (default) or 256x128x256 prolate capsule in shear")
     ap.add_argument("--serve-window", type=float, default=60.0)
     ap.add_argument("--sources-sha256", action="store_true",
                     help="print the hash of the sweep's sources and exit")
@@ -260,7 +278,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    job = I.prolate_shear(args.seed)
+    gen, mesh_text = WORKLOADS[args.workload]
+    job = getattr(I, gen)(args.seed)
     spec = job.lattice
     lat = api.Lattice(spec, stream=stream)
     b = lat.add_body(job.body, job.xyz, job.tri)
@@ -297,12 +316,12 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"prolate capsule in shear, {spec.nx}x{spec.ny}x{spec.nz} D3Q19, "
-                               f"level-4 mesh (2562 vertices, 5120 markers), tau={spec.tau:.4f} "
+                               f"{mesh_text}, tau={spec.tau:.4f} "
                                f"(seed {args.seed}), FP32 shifted populations",
-                   "lattice": [spec.nx, spec.ny, spec.nz], "markers": int(len(job.tri)),
+                   "lattice": [spec.nx, spec.ny, spec.nz], "markers": int(len(job.tri)), "name": args.workload,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload),
                      "kernel": "k_sweep<float,collide>",
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": round(sweep_avg_s * 1e6, 3)},

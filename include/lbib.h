@@ -62,13 +62,18 @@ typedef enum { LBIB_BC_PERIODIC = 0, LBIB_BC_ZOUHE_VELOCITY = 1, LBIB_BC_BOUNCEB
 
 /* Population storage.  All forms store the deviation g_i = f_i - w_i from the lattice
  * weights and collide in FP32; FP16/BF16 narrow with round-to-nearest-even and keep
- * subnormals. */
+ * subnormals.  FP16 holds g_i * 2^12 (an exact power-of-two scale that keeps small deviations
+ * in the normal range); BF16 holds g_i. */
 typedef enum { LBIB_STORE_F32 = 0, LBIB_STORE_F16 = 1, LBIB_STORE_BF16 = 2 } lbib_storage;
 
 /* Membrane vertex update.  DISPLACEMENT: position by Eq. (verletPos) with the interpolated
  * fluid velocity as tentative velocity, vertex velocity = displacement of the step.
- * PAPER: the printed three-stage verletPos / verletVel / verletPos sequence. */
-typedef enum { LBIB_INTEGRATOR_DISPLACEMENT = 0, LBIB_INTEGRATOR_PAPER = 1 } lbib_integrator;
+ * PAPER: the printed three-stage verletPos / verletVel / verletPos sequence.
+ * KINEMATIC: the kinematic immersed boundary the paper contrasts with the dynamic one
+ * (Sec. 2.4): every vertex is advected with the interpolated fluid velocity, x += u0; membrane
+ * forces are still evaluated and reported but do not move the vertices. */
+typedef enum { LBIB_INTEGRATOR_DISPLACEMENT = 0, LBIB_INTEGRATOR_PAPER = 1,
+               LBIB_INTEGRATOR_KINEMATIC = 2 } lbib_integrator;
 
 typedef struct {
     int32_t nx, ny, nz;

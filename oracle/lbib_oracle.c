@@ -37,6 +37,10 @@
  *   - rigid bodies: mass m = ratio * V0 (fluid density 1), net gravity (m - V0) g, inertia of
  *     the solid polyhedron rotated with the body, no gyroscopic term.
  *   - start-up of the multistep formulas from rest: x^{-1} = x^0, u^{-1} = 0.
+ *   - kinematic IB (Sec. 2.4 contrasts it with the dynamic scheme; it differs only in how the
+ *     points are displaced): x^{n+1} = x^n + u0 dt with u0 the MLS fluid velocity at the vertex
+ *     from f^{n+1}, vertex velocity u0.  Forcing and the membrane force evaluation are unchanged;
+ *     the membrane forces no longer move the vertices.
  *   - membrane vertex update (default): position from Eq. verletPos with the interpolated fluid
  *     velocity, vertex velocity = the displacement of that step.  The printed three-stage
  *     update (verletPos, verletVel, verletPos again) is one pass of the fixed-point map
@@ -650,7 +654,8 @@ int orc_body_add(orc_lattice* L, const orc_body_desc* d, const double* xyz, int3
     if (!(d->mls_rw > 0) || !(d->mls_alpha > 0)) { set_err("bad MLS parameters"); return ORC_EINVAL; }
     if (!d->rigid && !(d->mass_ratio > 0)) { set_err("membrane mass must be positive"); return ORC_EINVAL; }
     if (d->rigid && !(d->mass_ratio > 0)) { set_err("rigid density ratio must be positive"); return ORC_EINVAL; }
-    if (d->integrator != ORC_INTEGRATOR_DISPLACEMENT && d->integrator != ORC_INTEGRATOR_PAPER) {
+    if (d->integrator != ORC_INTEGRATOR_DISPLACEMENT && d->integrator != ORC_INTEGRATOR_PAPER &&
+        d->integrator != ORC_INTEGRATOR_KINEMATIC) {
         set_err("unknown integrator"); return ORC_EINVAL;
     }
     if (!d->rigid && (d->gravity[0] != 0 || d->gravity[1] != 0 || d->gravity[2] != 0)) {
@@ -1177,6 +1182,10 @@ static int structure_update(orc_lattice* L, body_t* b) {
             if (b->d.integrator == ORC_INTEGRATOR_PAPER) {
                 un = 1.5 * xt - 2.0 * b->x[i] + 0.5 * b->xprev[i]; /* Eq. (verletVel) */
                 xn = b->x[i] + un + 0.5 * acc;                    /* Eq. (verletPos) again */
+            } else if (b->d.integrator == ORC_INTEGRATOR_KINEMATIC) {
+                /* kinematic IB (Sec. 2.4): the point is advected with the fluid velocity */
+                un = u0[i];
+                xn = b->x[i] + un;
             } else {
                 xn = xt;
                 un = xn - b->x[i];

@@ -26,8 +26,9 @@ extern "C" {
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EUNSTABLE = -4, ORC_EDOMAIN = -7 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_ZOUHE = 1, ORC_BC_BOUNCEBACK = 2 };
 /* membrane vertex update: DISPLACEMENT = Eq. verletPos, velocity = displacement of the step;
- * PAPER = the three-stage update of Eqs. verletPos, verletVel, verletPos as printed */
-enum { ORC_INTEGRATOR_DISPLACEMENT = 0, ORC_INTEGRATOR_PAPER = 1 };
+ * PAPER = the three-stage update of Eqs. verletPos, verletVel, verletPos as printed;
+ * KINEMATIC = points advected with the interpolated fluid velocity (kinematic IB, Sec. 2.4) */
+enum { ORC_INTEGRATOR_DISPLACEMENT = 0, ORC_INTEGRATOR_PAPER = 1, ORC_INTEGRATOR_KINEMATIC = 2 };
 
 typedef struct {
     int32_t nx, ny, nz, pad;

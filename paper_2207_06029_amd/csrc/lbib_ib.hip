@@ -596,6 +596,10 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
                     // Eqs. (verletPos), (verletVel), (verletPos) as printed, in displacement form
                     un[a] = 1.5 * (u0[a] + 0.5 * acc) - 0.5 * (x[a] - P.xprev[3 * gv + a]);
                     dx = un[a] + 0.5 * acc;
+                } else if (B.integrator == 2) {
+                    // kinematic IB (Sec. 2.4): advected with the fluid velocity
+                    un[a] = u0[a];
+                    dx = un[a];
                 } else {
                     // Eq. (verletPos); vertex velocity = displacement of the step
                     dx = u0[a] + 0.5 * acc;

@@ -138,7 +138,7 @@ lbib_status build_body(const lbib_body_desc& d, const double* xyz, int nv, const
     if (!(d.mls_rw > 0) || !(d.mls_alpha > 0) || !(d.probe_len >= 0) || !(d.shell_h > 0))
         return fail(LBIB_EINVAL, "bad MLS / probe / shell parameters");
     if (!(d.mass_ratio > 0)) return fail(LBIB_EINVAL, "mass ratio must be positive");
-    if (d.integrator != 0 && d.integrator != 1) return fail(LBIB_EINVAL, "unknown integrator");
+    if (d.integrator < 0 || d.integrator > 2) return fail(LBIB_EINVAL, "unknown integrator");
     if (!d.rigid && (d.gravity[0] != 0 || d.gravity[1] != 0 || d.gravity[2] != 0))
         return fail(LBIB_EINVAL, "gravity is supported on rigid bodies only");
     for (int i = 0; i < 3 * nt; ++i)

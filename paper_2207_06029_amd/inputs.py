@@ -32,6 +32,7 @@ STORE_BF16 = 2
 
 INTEGRATOR_DISPLACEMENT = 0   # membrane position by Eq. verletPos, velocity = step displacement
 INTEGRATOR_PAPER = 1          # the printed three-stage verletPos / verletVel / verletPos update
+INTEGRATOR_KINEMATIC = 2      # kinematic IB: points advected with the interpolated fluid velocity
 
 # ---------------------------------------------------------------- meshes
 

@@ -26,13 +26,26 @@ def rel_l2(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_both(api, orc, job, steps, storage=None):
+def linear_shear(spec):
+    """rho = 1 and u_x = gamma (y - (ny-1)/2) with gamma set by the Zou-He wall speeds."""
+    n = spec.nx * spec.ny * spec.nz
+    gamma = (spec.wall_u[3][0] - spec.wall_u[2][0]) / (spec.ny - 1)
+    y = (np.arange(n) // spec.nx) % spec.ny
+    u = np.zeros((3, n))
+    u[0] = gamma * (y - (spec.ny - 1) / 2.0)
+    return np.ones(n), u
+
+
+def run_both(api, orc, job, steps, storage=None, init=None):
     spec = job.lattice
     if storage is not None:
         spec.storage = storage
     lat = api.Lattice(spec)
-    b = lat.add_body(job.body, job.xyz, job.tri)
     ref = orc.Lattice(spec)
+    if init is not None:
+        lat.init(*init)
+        ref.init(*init)
+    b = lat.add_body(job.body, job.xyz, job.tri)
     rb = ref.add_body(job.body, job.xyz, job.tri)
     lat.step(steps)
     ref.step(steps)
@@ -67,3 +80,43 @@ def test_settling_full_size_fp32(api, orc):
 def test_settling_full_size_fp16(api, orc):
     eu, ex = run_both(api, orc, I.settling_sphere(2.0, I.STORE_F16), 100)
     assert eu < 1e-3 and ex < 1e-3
+
+
+def test_prolate_large_fp32_sampled_steps(api, orc):
+    """256x128x256 with the level-5 mesh, in the launch configuration the benchmark times:
+    20 steps against the oracle (its full run length is out of the oracle's reach), started
+    from the developed linear shear so the capsule is loaded from the first step."""
+    job = I.prolate_shear_large(0)
+    eu, ex = run_both(api, orc, job, 20, init=linear_shear(job.lattice))
+    assert eu < 1e-5 and ex < 1e-5
+
+
+def _settle_trajectory(api, storage, ratio, steps, every):
+    job = I.settling_sphere(ratio, storage)
+    lat = api.Lattice(job.lattice)
+    b = lat.add_body(job.body, job.xyz, job.tri)
+    zs, ws = [], []
+    for _ in range(steps // every):
+        lat.step(every)
+        x, v = lat.body_state(b)
+        zs.append(x[:, 2].mean())
+        ws.append(v[:, 2].mean())
+    lat.destroy()
+    return job.xyz[:, 2].mean(), np.array(zs), np.array(ws)
+
+
+@pytest.mark.parametrize("ratio", [1.5, 8.0])
+def test_settling_20000_steps_reduced_storage_vs_fp32(api, ratio):
+    """Full settling run (96x96x384, 20000 steps): the centre trajectory with FP16 shifted storage
+    against the same run with FP32 storage; BF16 reported alongside."""
+    z0, z32, w32 = _settle_trajectory(api, I.STORE_F32, ratio, 20000, 1000)
+    _, z16, w16 = _settle_trajectory(api, I.STORE_F16, ratio, 20000, 1000)
+    _, zbf, wbf = _settle_trajectory(api, I.STORE_BF16, ratio, 20000, 1000)
+    e16 = rel_l2(z16 - z0, z32 - z0)
+    ebf = rel_l2(zbf - z0, z32 - z0)
+    v16 = rel_l2(w16, w32)
+    print(f"ratio {ratio}: fall {z0 - z32[-1]:.3f} lu, final u_z {w32[-1]:.3e}; "
+          f"FP16 displacement {e16:.3e} velocity {v16:.3e}; BF16 displacement {ebf:.3e} "
+          f"velocity {rel_l2(wbf, w32):.3e}")
+    assert z32[-1] < z0 - 1.0     # it does settle
+    assert e16 < 1e-3 and v16 < 1e-3

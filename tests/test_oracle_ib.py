@@ -178,7 +178,7 @@ def test_probe_stress_exact_for_linear_fields(orc):
     np.testing.assert_allclose(F, exact, rtol=0, atol=1e-10 * np.abs(exact).max())
 
 
-@pytest.mark.parametrize("rigid,integrator", [(False, 0), (False, 1), (True, 0)])
+@pytest.mark.parametrize("rigid,integrator", [(False, 0), (False, 1), (False, 2), (True, 0)])
 def test_galilean_translation(orc, rigid, integrator):
     """Uniform flow U0 in a periodic box carrying a body at its rest shape with velocity U0
     (previous positions x^0 - U0 set by set_velocity): no force arises, the fluid stays
