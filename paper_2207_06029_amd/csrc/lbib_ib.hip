@@ -8,12 +8,13 @@
 //
 // Step order inside the time step n -> n+1:
 //   k_centroids  triangle blocks: force window of this step from the vertex bounding box,
-//                geometry at x^n, MLS at centroids on moments of f^n, F_l = U_b - U*, fixed-point
-//                spreading into the body's force window, enclosed volume V^n (k_v != 0);
-//                edge blocks: spring and bending forces of every hinge at x^n
+//                geometry at x^n (kept for the probes), MLS at centroids on moments of f^n,
+//                F_l = U_b - U*, fixed-point spreading into the body's force window, enclosed
+//                volume V^n (k_v != 0); edge blocks: spring and bending forces of every hinge
 //   (sweep)      collide+stream with the spread force
 //   (moments)    moments of f^{n+1} in the body's window
-//   k_triangles  one group per probe: stresses on f^{n+1} (Eqs. hydroForP, hydroForNu), volume
+//   k_triangles  one group per probe (geometry from the centroid kernel): stresses on f^{n+1}
+//                (Eqs. hydroForP, hydroForNu), volume
 //                force per triangle; rigid bodies: FP64 totals and the velocity / pose update
 //                in the last block
 //   k_vertices   vertex velocity from the fluid, gathered forces, membrane update, integer
@@ -331,6 +332,11 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri) {
         }
         cross3(ab, ac, N);
         const double A = 0.5 * sqrt(dot3(N, N));
+        if (lane == 0) {
+            // geometry at x^n for the probes of this step
+            double* g = P.tgeo + 6 * (B.t0 + t);
+            for (int a = 0; a < 3; ++a) { g[a] = cen[a]; g[3 + a] = N[a]; }
+        }
         if (!B.rigid && B.kv != 0.0) {
             // signed volume of the tetrahedron (r, a, b, c), r = vertex 0 of the body
             double r0[3], pa[3], pb[3], pc[3], bc[3];
@@ -400,17 +406,9 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
     int err = 0;
     double cen[3] = {0, 0, 0}, N[3] = {0, 0, 0}, nrm[3] = {0, 0, 0}, A = 0.0;
     if (t < B.nt) {
-        const int* tv = P.tri + 3 * (B.t0 + t);
-        double xa[3], xb_[3], xc[3], ab[3], ac[3];
-        load3(P.x + 3 * (B.v0 + tv[0]), xa);
-        load3(P.x + 3 * (B.v0 + tv[1]), xb_);
-        load3(P.x + 3 * (B.v0 + tv[2]), xc);
-        for (int a = 0; a < 3; ++a) {
-            cen[a] = (xa[a] + xb_[a] + xc[a]) * (1.0 / 3.0);
-            ab[a] = xb_[a] - xa[a];
-            ac[a] = xc[a] - xa[a];
-        }
-        cross3(ab, ac, N);
+        // centroid and normal at x^n, as the centroid kernel of this step computed them
+        const double* g = P.tgeo + 6 * (B.t0 + t);
+        for (int a = 0; a < 3; ++a) { cen[a] = g[a]; N[a] = g[3 + a]; }
         const double ln = sqrt(dot3(N, N));
         A = 0.5 * ln;
         for (int a = 0; a < 3; ++a) nrm[a] = N[a] / ln;
@@ -551,20 +549,35 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
     int bl[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, bh[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
     if (v < B.nv) {
         const long long gv = B.v0 + v;
+        double x[3], xn[3];
+        load3(P.x + 3 * gv, x);
+        // membranes: stencil of the vertex and its moments first, so the load overlaps the
+        // force gathers below
+        MlsLane m;
+        float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (!B.rigid) {
+            mls_setup(J, x, B.rw, lane, m, err);
+            if (m.active) {
+                const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
+                if (l < 0) err |= FLAG_WINDOW;
+                else mom = P.mwin[B.win_off + l];
+            }
+        }
         // gathered forces: a third of each incident triangle's probe force, its volume force,
-        // the spring and bending forces of every incident hinge
+        // the spring and bending forces of every incident hinge; lane j takes entry j
         double f[3] = {0.0, 0.0, 0.0};
-        const int t_beg = P.vt_ptr[B.vt_off + v], t_end = P.vt_ptr[B.vt_off + v + 1];
-        for (int q = t_beg + lane; q < t_end; q += GROUP) {
-            const long long t = B.t0 + P.vt_list[q];
+        for (int j = lane; j < B.vt_w; j += GROUP) {
+            const int tl = P.vt_list[B.vt_off + (long long)v * B.vt_w + j];
+            if (tl < 0) continue;
+            const long long t = B.t0 + tl;
             for (int a = 0; a < 3; ++a) f[a] += P.fext[3 * t + a] * (1.0 / 3.0);
             if (!B.rigid)
                 for (int a = 0; a < 3; ++a) f[a] += P.fvol[3 * t + a];
         }
         if (!B.rigid) {
-            const int h_beg = P.vh_ptr[B.vh_off + v], h_end = P.vh_ptr[B.vh_off + v + 1];
-            for (int q = h_beg + lane; q < h_end; q += GROUP) {
-                const int code = P.vh_list[q];
+            for (int j = lane; j < B.vh_w; j += GROUP) {
+                const int code = P.vh_list[B.vh_off + (long long)v * B.vh_w + j];
+                if (code < 0) continue;
                 const double* fe = P.fedge + 15LL * (B.e0 + (code >> 2));
                 const int role = code & 3;
                 const double sgn = role == 0 ? 1.0 : (role == 1 ? -1.0 : 0.0);
@@ -572,18 +585,8 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
             }
         }
         const double F0 = gsum(f[0]), F1 = gsum(f[1]), F2 = gsum(f[2]);
-        double x[3], xn[3];
-        load3(P.x + 3 * gv, x);
         if (!B.rigid) {
             // tentative velocity: fluid velocity at the vertex from f^{n+1}
-            MlsLane m;
-            mls_setup(J, x, B.rw, lane, m, err);
-            float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (m.active) {
-                const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
-                if (l < 0) err |= FLAG_WINDOW;
-                else mom = P.mwin[B.win_off + l];
-            }
             mls_solve(m, B.alpha, false, err);
             const double u0[3] = {gsum(m.phi * (double)mom.y), gsum(m.phi * (double)mom.z),
                                   gsum(m.phi * (double)mom.w)};

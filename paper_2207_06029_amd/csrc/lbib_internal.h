@@ -106,8 +106,10 @@ struct BodyDev {
     long long win_off;          // offset of the body's windows in the window pools (nodes)
     int win_cap[3];             // reserved window extent per axis
     int red_slot;               // offset of this body's block partials
-    // CSR of incident triangles and hinge roles per vertex: offsets into the pointer pools
+    // incident triangles and hinge roles per vertex, padded to a fixed width per body:
+    // entry j of vertex v at list[off + v * w + j], -1 past the vertex's own count
     long long vt_off, vh_off;
+    int vt_w, vh_w;
     // first block of this body in the centroid / edge / triangle / vertex grids, block counts
     int blk_c0, nblk_c, blk_e0, nblk_e, blk_t0, nblk_t, blk_v0, nblk_v;
     double kb, kv, mv, V0, mass;
@@ -147,10 +149,9 @@ struct Pools {
     const double* l0;        // [ne]
     const double* ks;        // [ne]
     const double* theta0;    // [ne]
-    const int* vt_ptr;       // [nv+1 per body] incident triangles
-    const int* vt_list;
-    const int* vh_ptr;       // [nv+1 per body] incident hinges: 4*hinge + role
-    const int* vh_list;
+    const int* vt_list;      // [nv * vt_w per body] incident triangles (padded, -1)
+    const int* vh_list;      // [nv * vh_w per body] incident hinges: 4*hinge + role (padded, -1)
+    double* tgeo;            // [6 nt] centroid and area-weighted normal (x1-x0)x(x2-x0) at x^n
     double* fext;            // [3 nt] hydrodynamic force per triangle
     double* fvol;            // [3 nt] volume-penalty force per vertex of each triangle
     double* fedge;           // [15 ne] spring force on x1, bending force on x1..x4 per hinge

@@ -418,7 +418,7 @@ lbib_status Batch::rebuild_bodies() {
     std::vector<BodyDev> bd(hbodies.size());
     std::vector<int> bc, be, bt, bv, vbox;
     std::vector<double> x, xprev, uv, xb, l0, ks, th0;
-    std::vector<int> tri, edge, hinge, vtp, vtl, vhp, vhl;
+    std::vector<int> tri, edge, hinge, vtl, vhl;
     std::vector<WinDesc> fd(hbodies.size());
     std::vector<BodyState> bs(hbodies.size());
     long long v0 = 0, t0 = 0, e0 = 0, woff = 0, red = 0;
@@ -434,8 +434,26 @@ lbib_status Batch::rebuild_bodies() {
         B.job = h.job; B.rigid = h.desc.rigid; B.integrator = h.desc.integrator;
         B.nv = h.nv; B.nt = h.nt; B.ne = h.ne;
         B.v0 = v0; B.t0 = t0; B.e0 = e0;
-        B.vt_off = v0 + (long long)i;  // CSR pointer arrays hold nv+1 entries per body
-        B.vh_off = B.vt_off;
+        // padded incidence lists: width = the largest count of any vertex of this body
+        int wt = 1, wh = 1;
+        for (int v = 0; v < h.nv; ++v) {
+            wt = std::max(wt, h.vt_ptr[v + 1] - h.vt_ptr[v]);
+            wh = std::max(wh, h.vh_ptr[v + 1] - h.vh_ptr[v]);
+        }
+        B.vt_off = (long long)vtl.size();
+        B.vh_off = (long long)vhl.size();
+        B.vt_w = wt;
+        B.vh_w = wh;
+        for (int v = 0; v < h.nv; ++v) {
+            for (int j = 0; j < wt; ++j) {
+                const int q = h.vt_ptr[v] + j;
+                vtl.push_back(q < h.vt_ptr[v + 1] ? h.vt_list[q] : -1);
+            }
+            for (int j = 0; j < wh; ++j) {
+                const int q = h.vh_ptr[v] + j;
+                vhl.push_back(q < h.vh_ptr[v + 1] ? h.vh_list[q] : -1);
+            }
+        }
         B.kb = h.desc.kb; B.kv = h.desc.kv; B.mv = h.mv; B.V0 = h.V0; B.mass = h.mass;
         B.rw = h.desc.mls_rw; B.alpha = h.desc.mls_alpha; B.probe = h.desc.probe_len; B.shell_h = h.desc.shell_h;
         for (int a = 0; a < 3; ++a) B.gravity[a] = h.desc.gravity[a];
@@ -470,14 +488,6 @@ lbib_status Batch::rebuild_bodies() {
         l0.insert(l0.end(), h.l0.begin(), h.l0.end());
         ks.insert(ks.end(), h.ks.begin(), h.ks.end());
         th0.insert(th0.end(), h.theta0.begin(), h.theta0.end());
-        // CSR pointers are stored relative to this body's list offsets
-        const int ot = (int)vtl.size(), oh = (int)vhl.size();
-        for (int v = 0; v <= h.nv; ++v) {
-            vtp.push_back(ot + h.vt_ptr[v]);
-            vhp.push_back(oh + h.vh_ptr[v]);
-        }
-        vtl.insert(vtl.end(), h.vt_list.begin(), h.vt_list.end());
-        vhl.insert(vhl.end(), h.vh_list.begin(), h.vh_list.end());
         v0 += h.nv; t0 += h.nt; e0 += h.ne;
         // state
         BodyState& S = bs[i];
@@ -523,13 +533,13 @@ lbib_status Batch::rebuild_bodies() {
     if ((st = upload(arena, l0, (double**)&P.l0, stream))) return st;
     if ((st = upload(arena, ks, (double**)&P.ks, stream))) return st;
     if ((st = upload(arena, th0, (double**)&P.theta0, stream))) return st;
-    if ((st = upload(arena, vtp, (int**)&P.vt_ptr, stream))) return st;
     if ((st = upload(arena, vtl, (int**)&P.vt_list, stream))) return st;
-    if ((st = upload(arena, vhp, (int**)&P.vh_ptr, stream))) return st;
     if ((st = upload(arena, vhl, (int**)&P.vh_list, stream))) return st;
     std::vector<double> fe(3 * (size_t)std::max<long long>(t0, 1), 0.0);
     if ((st = upload(arena, fe, &P.fext, stream))) return st;
     if ((st = upload(arena, fe, &P.fvol, stream))) return st;
+    std::vector<double> tg(6 * (size_t)std::max<long long>(t0, 1), 0.0);
+    if ((st = upload(arena, tg, &P.tgeo, stream))) return st;
     std::vector<double> fedge(15 * (size_t)std::max<long long>(e0, 1), 0.0);
     if ((st = upload(arena, fedge, &P.fedge, stream))) return st;
     void* p;
