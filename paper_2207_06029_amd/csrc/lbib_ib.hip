@@ -263,7 +263,7 @@ __device__ void hinge_forces(const Pools& P, const BodyDev& B, int e, double out
 }
 
 // ---------------------------------------------------------------- centroids (+ hinges)
-__global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri) {
+__global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fold) {
     if ((int)blockIdx.x >= nblk_tri) {
         // edge blocks: one thread per hinge of a membrane
         const int eb = blockIdx.x - nblk_tri;
@@ -301,27 +301,33 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri) {
                 Ub[a] = (P.uv[3 * (B.v0 + tv[0]) + a] + P.uv[3 * (B.v0 + tv[1]) + a] +
                          P.uv[3 * (B.v0 + tv[2]) + a]) * (1.0 / 3.0);
     }
-    // this step's force window: the first wave folds the integer boxes the vertex blocks wrote
-    // for x^n (min / max, order independent); every block derives the same descriptor and
-    // block 0 publishes it for the sweep and the moments
-    if (threadIdx.x < 64) {
-        int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
-        for (int q = threadIdx.x; q < B.nblk_v; q += 64) {
-            const int* vb = P.vbox + 6LL * (B.blk_v0 + q);
-            for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], vb[a]); hi[a] = max(hi[a], vb[3 + a]); }
-        }
-        for (int o = 32; o >= 1; o >>= 1)
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
-                hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
+    // this step's force window.  fold: the first wave folds the integer boxes the vertex
+    // blocks wrote for x^n (min / max, order independent); every block derives the same
+    // descriptor and block 0 publishes it for the sweep and the moments.  Otherwise the window
+    // kernel of the previous step has published it already.
+    WinDesc fd;
+    if (fold) {
+        if (threadIdx.x < 64) {
+            int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
+            for (int q = threadIdx.x; q < B.nblk_v; q += 64) {
+                const int* vb = P.vbox + 6LL * (B.blk_v0 + q);
+                for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], vb[a]); hi[a] = max(hi[a], vb[3 + a]); }
             }
-        if (threadIdx.x == 0)
-            for (int a = 0; a < 3; ++a) { sbox[a] = lo[a]; sbox[3 + a] = hi[a]; }
+            for (int o = 32; o >= 1; o >>= 1)
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
+                    hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
+                }
+            if (threadIdx.x == 0)
+                for (int a = 0; a < 3; ++a) { sbox[a] = lo[a]; sbox[3 + a] = hi[a]; }
+        }
+        __syncthreads();
+        const int bmin[3] = {sbox[0], sbox[1], sbox[2]}, bmax[3] = {sbox[3], sbox[4], sbox[5]};
+        fd = window_from_box(J, B, bmin, bmax, err);
+        if (blk == 0 && threadIdx.x == 0) P.fdesc[b] = fd;
+    } else {
+        fd = P.fdesc[b];
     }
-    __syncthreads();
-    const int bmin[3] = {sbox[0], sbox[1], sbox[2]}, bmax[3] = {sbox[3], sbox[4], sbox[5]};
-    const WinDesc fd = window_from_box(J, B, bmin, bmax, err);
-    if (blk == 0 && threadIdx.x == 0) P.fdesc[b] = fd;
     double Vt = 0.0;
     if (live) {
         double cen[3], ab[3], ac[3], N[3];
@@ -652,6 +658,37 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
     }
 }
 
+// ---------------------------------------------------------------- windows of the next step
+// One block per body: fold the integer boxes of x^{n+1} the vertex blocks wrote and publish the
+// force window of the next step (used for batches, where folding once per body is cheaper than
+// once per centroid block).
+__global__ void __launch_bounds__(256) k_windows(Pools P) {
+    const int b = blockIdx.x;
+    const BodyDev& B = P.bodies[b];
+    const JobDev& J = P.jobs[B.job];
+    __shared__ int red[6][256];
+    const int t = threadIdx.x;
+    int e[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -0x7fffffff, -0x7fffffff, -0x7fffffff};
+    for (int q = t; q < B.nblk_v; q += 256) {
+        const int* vb = P.vbox + 6LL * (B.blk_v0 + q);
+        for (int a = 0; a < 3; ++a) { e[a] = min(e[a], vb[a]); e[3 + a] = max(e[3 + a], vb[3 + a]); }
+    }
+    for (int a = 0; a < 6; ++a) red[a][t] = e[a];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w)
+            for (int a = 0; a < 6; ++a)
+                red[a][t] = a < 3 ? min(red[a][t], red[a][t + w]) : max(red[a][t], red[a][t + w]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        int err = 0;
+        const int bmin[3] = {red[0][0], red[1][0], red[2][0]}, bmax[3] = {red[3][0], red[4][0], red[5][0]};
+        P.fdesc[b] = window_from_box(J, B, bmin, bmax, err);
+        if (err) atomicOr(P.flags + B.job, err);
+    }
+}
+
 // ---------------------------------------------------------------- reported totals (membranes)
 // FP64 hydrodynamic force and torque of the last step, torque about the vertex mean of x^n
 // (held in xprev after the update).  One block, fixed-shape tree: reproducible.
@@ -691,9 +728,12 @@ __global__ void __launch_bounds__(256) k_body_totals(Pools P, int b, double* out
     if (t < 6) out[t] = red[t][0];
 }
 
-void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, hipStream_t s) {
+void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, bool fold, hipStream_t s) {
     if (nblk_tri + nblk_edge > 0)
-        hipLaunchKernelGGL(k_centroids, dim3(nblk_tri + nblk_edge), dim3(256), 0, s, P, nblk_tri);
+        hipLaunchKernelGGL(k_centroids, dim3(nblk_tri + nblk_edge), dim3(256), 0, s, P, nblk_tri, (int)fold);
+}
+void launch_windows(const Pools& P, int nbodies, hipStream_t s) {
+    if (nbodies > 0) hipLaunchKernelGGL(k_windows, dim3(nbodies), dim3(256), 0, s, P);
 }
 void launch_triangles(const Pools& P, int nblocks, hipStream_t s) {
     if (nblocks > 0) hipLaunchKernelGGL(k_triangles, dim3(nblocks), dim3(256), 0, s, P);

@@ -22,6 +22,8 @@ constexpr int WIN_MARGIN = 4;    // nodes around a body's bounding box (probe + 
 constexpr int GROUP = 32;        // lanes that evaluate one MLS point
 constexpr int MLS_PER_BLOCK = 8; // MLS points (32-lane groups) per 256-thread block
 constexpr int MAX_RED_BLOCKS = 65536;
+// window-moments blocks per body: one 256-thread block per this many nodes of window capacity
+constexpr int WIN_NODES_PER_BLOCK = 2048;
 
 // error flag bits (per job)
 constexpr int FLAG_DOMAIN = 1;     // a support or probe reached a wall node / left the domain
@@ -111,7 +113,7 @@ struct BodyDev {
     long long vt_off, vh_off;
     int vt_w, vh_w;
     // first block of this body in the centroid / edge / triangle / vertex grids, block counts
-    int blk_c0, nblk_c, blk_e0, nblk_e, blk_t0, nblk_t, blk_v0, nblk_v;
+    int blk_c0, nblk_c, blk_e0, nblk_e, blk_t0, nblk_t, blk_v0, nblk_v, blk_w0, nblk_w;
     double kb, kv, mv, V0, mass;
     double rw, alpha, probe, shell_h;
     double gravity[3];
@@ -138,6 +140,7 @@ struct Pools {
     const int* blk_body_e;   // block -> body for the edge blocks of the centroid kernel
     const int* blk_body_t;
     const int* blk_body_v;
+    const int* blk_body_w;   // block -> body for the window-moments kernel
     double* x;               // [3 nv] positions x^n (all bodies concatenated)
     double* xprev;           // [3 nv] x^{n-1}
     double* uv;              // [3 nv] vertex velocity u_v^n
@@ -176,8 +179,8 @@ struct SweepShape {
 // and end on the device), not by separate stream commands around it.
 void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int ntiles,
                   SweepShape shape, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-void launch_window_moments(const Pools& P, int storage, bool from_b, int nbodies, int max_cap,
-                           hipStream_t s);
+// nblk_w: total window blocks (each body gets blocks in proportion to its window capacity)
+void launch_window_moments(const Pools& P, int storage, bool from_b, int nblk_w, hipStream_t s);
 void launch_macros(const Pools& P, int storage, bool from_b, int job, long long n, float* out4,
                    hipStream_t s);
 void launch_get_pops(const Pools& P, int storage, bool from_b, int job, long long n, float* out,
@@ -188,7 +191,12 @@ void launch_init_eq(int job, long long n, const double* rho, const double* u, do
                     hipStream_t s);
 
 // lbib_ib.hip
-void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, hipStream_t s);
+// fold: the centroid blocks derive this step's force window from the vertex-block boxes
+// themselves; otherwise launch_windows after the vertex kernel has published it.
+void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, bool fold, hipStream_t s);
+void launch_windows(const Pools& P, int nbodies, hipStream_t s);
+// bodies from which the force windows are folded once per body by a kernel of their own
+constexpr int WINDOW_KERNEL_MIN_BODIES = 2;
 void launch_triangles(const Pools& P, int nblocks, hipStream_t s);
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s);
 void launch_body_totals(const Pools& P, int body, double* out6, hipStream_t s);

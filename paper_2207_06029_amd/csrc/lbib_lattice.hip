@@ -282,51 +282,54 @@ void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int nt
 // (rho - 1, u*) with u* = sum f e / rho, and clear the force window for the next step.
 template <typename S>
 __global__ void __launch_bounds__(256) k_window_moments(Pools P, int from_b) {
-    const int b = blockIdx.y;
+    // blocks of a body are proportional to its window capacity; they stride over the current
+    // window, which is usually far smaller than the capacity
+    const int b = P.blk_body_w[blockIdx.x];
     const BodyDev& B = P.bodies[b];
     const JobDev& J = P.jobs[B.job];
+    const int lb = blockIdx.x - B.blk_w0;
     const WinDesc d = P.fdesc[b];
     const int dims[3] = {J.nx, J.ny, J.nz};
     if (!win_valid(d, dims, B.win_cap, J.bc)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(P.flags + B.job, FLAG_WINDOW);
+        if (lb == 0 && threadIdx.x == 0) atomicOr(P.flags + B.job, FLAG_WINDOW);
         return;
     }
-    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.mdesc[b] = d;
+    if (lb == 0 && threadIdx.x == 0) P.mdesc[b] = d;
     const long long nw = (long long)d.w[0] * d.w[1] * d.w[2];
-    if (l >= nw) return;
-    const int lx = (int)(l % d.w[0]);
-    const int ly = (int)((l / d.w[0]) % d.w[1]);
-    const int lz = (int)(l / ((long long)d.w[0] * d.w[1]));
-    int x = d.o[0] + lx, y = d.o[1] + ly, z = d.o[2] + lz;
-    if (x >= J.nx) x -= J.nx;
-    if (y >= J.ny) y -= J.ny;
-    if (z >= J.nz) z -= J.nz;
-    const long long k = x + (long long)J.nx * (y + (long long)J.ny * z);
-    const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
-    float g[Q];
-    pull<S>(src, J, x, y, z, k, g);
-    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        drho += g[i];
-        jx += cx(i) * g[i];
-        jy += cy(i) * g[i];
-        jz += cz(i) * g[i];
-    }
-    const float ir = 1.f / (1.f + drho);
-    P.mwin[B.win_off + l] = make_float4(drho, jx * ir, jy * ir, jz * ir);
     const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
-    long long* fw = P.fwin + 3 * B.win_off + l;
-    fw[0] = 0;
-    fw[capn] = 0;
-    fw[2 * capn] = 0;
+    const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
+    const long long stride = (long long)B.nblk_w * blockDim.x;
+    for (long long l = (long long)lb * blockDim.x + threadIdx.x; l < nw; l += stride) {
+        const int lx = (int)(l % d.w[0]);
+        const int ly = (int)((l / d.w[0]) % d.w[1]);
+        const int lz = (int)(l / ((long long)d.w[0] * d.w[1]));
+        int x = d.o[0] + lx, y = d.o[1] + ly, z = d.o[2] + lz;
+        if (x >= J.nx) x -= J.nx;
+        if (y >= J.ny) y -= J.ny;
+        if (z >= J.nz) z -= J.nz;
+        const long long k = x + (long long)J.nx * (y + (long long)J.ny * z);
+        float g[Q];
+        pull<S>(src, J, x, y, z, k, g);
+        float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            drho += g[i];
+            jx += cx(i) * g[i];
+            jy += cy(i) * g[i];
+            jz += cz(i) * g[i];
+        }
+        const float ir = 1.f / (1.f + drho);
+        P.mwin[B.win_off + l] = make_float4(drho, jx * ir, jy * ir, jz * ir);
+        long long* fw = P.fwin + 3 * B.win_off + l;
+        fw[0] = 0;
+        fw[capn] = 0;
+        fw[2 * capn] = 0;
+    }
 }
 
-void launch_window_moments(const Pools& P, int storage, bool from_b, int nbodies, int max_cap,
-                           hipStream_t s) {
-    if (nbodies <= 0) return;
-    dim3 grid((max_cap + 255) / 256, nbodies), block(256);
+void launch_window_moments(const Pools& P, int storage, bool from_b, int nblk_w, hipStream_t s) {
+    if (nblk_w <= 0) return;
+    dim3 grid(nblk_w), block(256);
     if (storage == 0) hipLaunchKernelGGL(k_window_moments<float>, grid, block, 0, s, P, (int)from_b);
     else if (storage == 1) hipLaunchKernelGGL(k_window_moments<__half>, grid, block, 0, s, P, (int)from_b);
     else hipLaunchKernelGGL(k_window_moments<__hip_bfloat16>, grid, block, 0, s, P, (int)from_b);

@@ -416,14 +416,14 @@ lbib_status Batch::rebuild_bodies() {
     std::stable_sort(hbodies.begin(), hbodies.end(), [](const HostBody& a, const HostBody& b) { return a.job < b.job; });
     for (auto& J : jobs) { J.body0 = 0; J.nbodies = 0; }
     std::vector<BodyDev> bd(hbodies.size());
-    std::vector<int> bc, be, bt, bv, vbox;
+    std::vector<int> bc, be, bt, bv, bw, vbox;
     std::vector<double> x, xprev, uv, xb, l0, ks, th0;
     std::vector<int> tri, edge, hinge, vtl, vhl;
     std::vector<WinDesc> fd(hbodies.size());
     std::vector<BodyState> bs(hbodies.size());
     long long v0 = 0, t0 = 0, e0 = 0, woff = 0, red = 0;
     max_cap = 0;
-    nblk_c = nblk_e = nblk_t = nblk_v = 0;
+    nblk_c = nblk_e = nblk_t = nblk_v = nblk_w = 0;
     for (size_t i = 0; i < hbodies.size(); ++i) {
         HostBody& h = hbodies[i];
         JobDev& J = jobs[h.job];
@@ -472,6 +472,9 @@ lbib_status Batch::rebuild_bodies() {
         B.blk_e0 = nblk_e; B.nblk_e = nbe; nblk_e += nbe;
         B.blk_t0 = nblk_t; B.nblk_t = nbt; nblk_t += nbt;
         B.blk_v0 = nblk_v; B.nblk_v = nbv; nblk_v += nbv;
+        const int nbw = (int)std::max<long long>(1, (capn + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
+        B.blk_w0 = nblk_w; B.nblk_w = nbw; nblk_w += nbw;
+        for (int k = 0; k < nbw; ++k) bw.push_back((int)i);
         for (int k = 0; k < nbc; ++k) bc.push_back((int)i);
         for (int k = 0; k < nbe; ++k) be.push_back((int)i);
         for (int k = 0; k < nbt; ++k) bt.push_back((int)i);
@@ -518,6 +521,7 @@ lbib_status Batch::rebuild_bodies() {
     if ((st = upload(arena, be, (int**)&P.blk_body_e, stream))) return st;
     if ((st = upload(arena, bt, (int**)&P.blk_body_t, stream))) return st;
     if ((st = upload(arena, bv, (int**)&P.blk_body_v, stream))) return st;
+    if ((st = upload(arena, bw, (int**)&P.blk_body_w, stream))) return st;
     if ((st = upload(arena, x, &P.x, stream))) return st;
     if ((st = upload(arena, xprev, &P.xprev, stream))) return st;
     if ((st = upload(arena, uv, &P.uv, stream))) return st;
@@ -699,7 +703,7 @@ lbib_status Batch::get_populations(int job, double* f) {
 
 // ---------------------------------------------------------------- stepping
 lbib_status Batch::prime() {
-    launch_window_moments(P, storage, cur_b, nbodies, (int)max_cap, stream);
+    launch_window_moments(P, storage, cur_b, nblk_w, stream);
     HIP_TRY(hipGetLastError());
     primed = true;
     return LBIB_OK;
@@ -707,7 +711,8 @@ lbib_status Batch::prime() {
 
 lbib_status Batch::enqueue_step(bool collide) {
     const bool bodies = collide && nbodies > 0;
-    if (bodies) launch_centroids(P, nblk_c, nblk_e, stream);
+    const bool fold_once = nbodies >= WINDOW_KERNEL_MIN_BODIES;
+    if (bodies) launch_centroids(P, nblk_c, nblk_e, !fold_once, stream);
     if (timing) {
         hipEvent_t a, b;
         lbib_status st = next_event(&a);
@@ -720,9 +725,10 @@ lbib_status Batch::enqueue_step(bool collide) {
     }
     cur_b = !cur_b;
     if (bodies) {
-        launch_window_moments(P, storage, cur_b, nbodies, (int)max_cap, stream);
+        launch_window_moments(P, storage, cur_b, nblk_w, stream);
         launch_triangles(P, nblk_t, stream);
         launch_vertices(P, nblk_v, stream);
+        if (fold_once) launch_windows(P, nbodies, stream);
     }
     HIP_TRY(hipGetLastError());
     return LBIB_OK;

@@ -108,3 +108,30 @@ def test_server_results_match_alone(api):
         alone.step(job.steps)
         x_a, _ = alone.lattice(0).body_state(0)
         np.testing.assert_array_equal(r["xyz"], x_a)
+
+
+def test_server_alone_vs_mix_24_stream_jobs(api):
+    """24 jobs from the serving-stream generator (capsule-shear and settling, uneven sizes and
+    run lengths) served with 8 slots: every result equals the same job run alone, bitwise."""
+    jobs = I.serving_stream(seed=7, rate_per_s=1e6, window_s=1.0, storage=I.STORE_F16,
+                            steps_range=(40, 200), levels=(2, 3),
+                            lattices=((32, 32, 32), (40, 32, 40), (48, 48, 48)), max_jobs=24)
+    assert len(jobs) == 24 and {j.kind for j in jobs} == {"shear", "settling"}
+    srv = api.Server(hbm_budget_bytes=1 << 34, max_slots=8, steps_per_tick=24, storage=I.STORE_F16)
+    ids = {srv.submit(job): job for job in jobs}
+    results = {}
+    for _ in range(400):
+        srv.tick()
+        for r in srv.poll(with_positions=True):
+            results[r["id"]] = r
+        if len(results) == len(jobs):
+            break
+    assert len(results) == len(jobs)
+    for jid, job in ids.items():
+        r = results[jid]
+        assert r["status"] == 0 and r["steps_done"] == job.steps, (job.name, r["status"])
+        alone = api.Batch([job], storage=I.STORE_F16)
+        alone.step(job.steps)
+        x_a, _ = alone.lattice(0).body_state(0)
+        np.testing.assert_array_equal(r["xyz"], x_a)
+        alone.destroy()
