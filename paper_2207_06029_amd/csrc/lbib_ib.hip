@@ -1,10 +1,10 @@
 // Immersed-boundary and structure kernels (Secs. 1.2-1.3).
 //
-// One MLS point (triangle centroid, probe or vertex) is evaluated by a group of 32 lanes; lane
-// k < 27 owns node k of the 3x3x3 block around the nearest node.  Every node within r_w of the
-// point lies in that block, so the group covers the whole support of Eq. (intKernel).  The
-// 4x4 moment matrix is accumulated and factorised in FP64 (every lane solves redundantly), so
-// no lane waits on another except for the butterfly sums.
+// One MLS point (triangle centroid, probe or vertex) is evaluated by a group of 16 lanes (one
+// DPP row); lane k owns nodes k and k + 16 of the 3x3x3 block around the nearest node.  Every
+// node within r_w of the point lies in that block, so the group covers the whole support of
+// Eq. (intKernel).  The 4x4 moment matrix is accumulated and factorised in FP64 (every lane
+// solves redundantly), so no lane waits on another except for the row butterfly sums.
 //
 // Step order inside the time step n -> n+1:
 //   k_centroids  triangle blocks: force window of this step from the vertex bounding box,
@@ -23,11 +23,11 @@
 
 namespace lbib {
 
-// Sum over the 32 lanes of an MLS group.  Lane exchanges xor 1 and xor 2 are quad permutes,
-// then row half-mirror and row mirror pair the 4- and 8-lane halves (after the previous levels
-// every lane of a block holds the same partial, so a mirror acts as an exchange), and the
-// 16-lane halves meet through a lane permute.  Each level adds the same two operands on both
-// partners, so every lane ends with the identical sum.
+// Sum over the 16 lanes of an MLS group (one DPP row).  Lane exchanges xor 1 and xor 2 are
+// quad permutes, then row half-mirror and row mirror pair the 4- and 8-lane halves (after the
+// previous levels every lane of a block holds the same partial, so a mirror acts as an
+// exchange).  Each level adds the same two operands on both partners, so every lane ends with
+// the identical sum, and no value leaves the row.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
@@ -39,7 +39,6 @@ __device__ __forceinline__ double gsum(double v) {
     v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
     v += dpp_f64<0x141>(v);  // row_half_mirror
     v += dpp_f64<0x140>(v);  // row_mirror
-    v += __shfl_xor(v, 16, GROUP);
     return v;
 }
 
@@ -47,33 +46,38 @@ __device__ __forceinline__ double agent_load(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One MLS point, per lane: lane k < 27 owns node k of the 3x3x3 block around the nearest node.
-// mls_setup finds the node, its offset d = x_k - x, r = |d| / r_w and whether it supports the
-// point (r <= 1); the caller then issues its field loads, and mls_solve builds and solves the
-// moment system while those loads are in flight.
+// One MLS point, per lane of its 16-lane group: lane k owns nodes k and k + 16 (when < 27) of
+// the 3x3x3 block around the nearest node.  mls_setup finds each node, its offset d = x_k - x,
+// r = |d| / r_w and whether it supports the point (r <= 1); the caller then issues its field
+// loads, and mls_solve builds and solves the moment system while those loads are in flight.
+constexpr int MLS_NODES = 2;   // stencil nodes per lane
 struct MlsLane {
-    bool active;
-    int gx, gy, gz;
-    double d0, d1, d2, r;
-    double phi;
-    double gr[3];
+    bool active[MLS_NODES];
+    int gx[MLS_NODES], gy[MLS_NODES], gz[MLS_NODES];
+    double d0[MLS_NODES], d1[MLS_NODES], d2[MLS_NODES], r[MLS_NODES];
+    double phi[MLS_NODES];
+    double gr[MLS_NODES][3];
 };
 
 __device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], double rw, int lane,
                                           MlsLane& m, int& err) {
     const int c0 = (int)floor(xp[0] + 0.5), c1 = (int)floor(xp[1] + 0.5), c2 = (int)floor(xp[2] + 0.5);
-    m.active = false;
-    m.d0 = m.d1 = m.d2 = 0.0;
-    m.r = 2.0;
-    m.gr[0] = m.gr[1] = m.gr[2] = 0.0;
-    if (lane < 27) {
-        int nn[3] = {c0 + lane % 3 - 1, c1 + (lane / 3) % 3 - 1, c2 + lane / 9 - 1};
-        m.d0 = nn[0] - xp[0];
-        m.d1 = nn[1] - xp[1];
-        m.d2 = nn[2] - xp[2];
-        m.r = sqrt(m.d0 * m.d0 + m.d1 * m.d1 + m.d2 * m.d2) / rw;
-        m.active = m.r <= 1.0;
-        const int dims[3] = {J.nx, J.ny, J.nz};
+    const int dims[3] = {J.nx, J.ny, J.nz};
+#pragma unroll
+    for (int s = 0; s < MLS_NODES; ++s) {
+        const int k = lane + GROUP * s;
+        m.active[s] = false;
+        m.d0[s] = m.d1[s] = m.d2[s] = 0.0;
+        m.r[s] = 2.0;
+        m.gr[s][0] = m.gr[s][1] = m.gr[s][2] = 0.0;
+        m.gx[s] = m.gy[s] = m.gz[s] = 0;
+        if (k >= 27) continue;
+        int nn[3] = {c0 + k % 3 - 1, c1 + (k / 3) % 3 - 1, c2 + k / 9 - 1};
+        m.d0[s] = nn[0] - xp[0];
+        m.d1[s] = nn[1] - xp[1];
+        m.d2[s] = nn[2] - xp[2];
+        m.r[s] = sqrt(m.d0[s] * m.d0[s] + m.d1[s] * m.d1[s] + m.d2[s] * m.d2[s]) / rw;
+        m.active[s] = m.r[s] <= 1.0;
         for (int a = 0; a < 3; ++a) {
             const int bc = J.bc[2 * a];
             if (bc == 0) {
@@ -82,27 +86,35 @@ __device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], d
             } else {
                 const int lo = bc == 1 ? 1 : 0, hi = bc == 1 ? dims[a] - 2 : dims[a] - 1;
                 if (nn[a] < lo || nn[a] > hi) {
-                    if (m.active) err |= FLAG_DOMAIN;
+                    if (m.active[s]) err |= FLAG_DOMAIN;
                     nn[a] = nn[a] < lo ? lo : hi;
                 }
             }
         }
-        m.gx = nn[0]; m.gy = nn[1]; m.gz = nn[2];
+        m.gx[s] = nn[0]; m.gy[s] = nn[1]; m.gz[s] = nn[2];
     }
 }
 
 // Shape functions phi_k = [A^{-1} W_k p_k]_0 and (optionally) their gradients, A = sum W p p^T,
 // p = (1, d), W = exp(-(r/alpha)^2) (Eqs. l2norm, intKernel).  FP64, Cholesky on every lane.
 __device__ __forceinline__ void mls_solve(MlsLane& m, double alpha, bool want_grad, int& err) {
-    double W = 0.0;
-    if (m.active) {
-        const double q = m.r / alpha;
-        W = exp(-q * q);
+    double W[MLS_NODES];
+    double s00 = 0, s01 = 0, s02 = 0, s03 = 0, s11 = 0, s12 = 0, s13 = 0, s22 = 0, s23 = 0, s33 = 0;
+#pragma unroll
+    for (int s = 0; s < MLS_NODES; ++s) {
+        W[s] = 0.0;
+        if (m.active[s]) {
+            const double q = m.r[s] / alpha;
+            W[s] = exp(-q * q);
+        }
+        const double w = W[s], d0 = m.d0[s], d1 = m.d1[s], d2 = m.d2[s];
+        s00 += w; s01 += w * d0; s02 += w * d1; s03 += w * d2;
+        s11 += w * d0 * d0; s12 += w * d0 * d1; s13 += w * d0 * d2;
+        s22 += w * d1 * d1; s23 += w * d1 * d2; s33 += w * d2 * d2;
     }
-    const double d0 = m.d0, d1 = m.d1, d2 = m.d2;
-    const double a00 = gsum(W), a01 = gsum(W * d0), a02 = gsum(W * d1), a03 = gsum(W * d2);
-    const double a11 = gsum(W * d0 * d0), a12 = gsum(W * d0 * d1), a13 = gsum(W * d0 * d2);
-    const double a22 = gsum(W * d1 * d1), a23 = gsum(W * d1 * d2), a33 = gsum(W * d2 * d2);
+    const double a00 = gsum(s00), a01 = gsum(s01), a02 = gsum(s02), a03 = gsum(s03);
+    const double a11 = gsum(s11), a12 = gsum(s12), a13 = gsum(s13);
+    const double a22 = gsum(s22), a23 = gsum(s23), a33 = gsum(s33);
     // Cholesky A = L L^T with reciprocal diagonals
     const double l00 = sqrt(a00), i00 = 1.0 / l00;
     const double l10 = a01 * i00, l20 = a02 * i00, l30 = a03 * i00;
@@ -112,17 +124,20 @@ __device__ __forceinline__ void mls_solve(MlsLane& m, double alpha, bool want_gr
     const double l32 = (a23 - l30 * l20 - l31 * l21) * i22;
     const double l33 = sqrt(a33 - l30 * l30 - l31 * l31 - l32 * l32), i33 = 1.0 / l33;
     if (!(l33 > 0.0) || !(l22 > 0.0) || !(l11 > 0.0) || !(l00 > 0.0)) err |= FLAG_NONFINITE;
-    // v = A^{-1} p_k: forward then back substitution
-    const double y0 = i00;
-    const double y1 = (d0 - l10 * y0) * i11;
-    const double y2 = (d1 - l20 * y0 - l21 * y1) * i22;
-    const double y3 = (d2 - l30 * y0 - l31 * y1 - l32 * y2) * i33;
-    const double v3 = y3 * i33;
-    const double v2 = (y2 - l32 * v3) * i22;
-    const double v1 = (y1 - l21 * v2 - l31 * v3) * i11;
-    const double v0 = (y0 - l10 * v1 - l20 * v2 - l30 * v3) * i00;
-    m.phi = W * v0;
-    if (want_grad) { m.gr[0] = W * v1; m.gr[1] = W * v2; m.gr[2] = W * v3; }
+#pragma unroll
+    for (int s = 0; s < MLS_NODES; ++s) {
+        // v = A^{-1} p_k: forward then back substitution
+        const double y0 = i00;
+        const double y1 = (m.d0[s] - l10 * y0) * i11;
+        const double y2 = (m.d1[s] - l20 * y0 - l21 * y1) * i22;
+        const double y3 = (m.d2[s] - l30 * y0 - l31 * y1 - l32 * y2) * i33;
+        const double v3 = y3 * i33;
+        const double v2 = (y2 - l32 * v3) * i22;
+        const double v1 = (y1 - l21 * v2 - l31 * v3) * i11;
+        const double v0 = (y0 - l10 * v1 - l20 * v2 - l30 * v3) * i00;
+        m.phi[s] = W[s] * v0;
+        if (want_grad) { m.gr[s][0] = W[s] * v1; m.gr[s][1] = W[s] * v2; m.gr[s][2] = W[s] * v3; }
+    }
 }
 
 // Window-local index of a node, or -1 if outside.
@@ -136,6 +151,19 @@ __device__ __forceinline__ long long win_index(const JobDev& J, const WinDesc& d
     if (lz < 0) lz += J.nz;
     if (lx >= d.w[0] || ly >= d.w[1] || lz >= d.w[2]) return -1;
     return lx + (long long)d.w[0] * (ly + (long long)d.w[1] * lz);
+}
+
+// Moments (rho - 1, u*) of the lane's active stencil nodes from the body's moment window.
+__device__ __forceinline__ void mls_moments(const Pools& P, const JobDev& J, const BodyDev& B, int b,
+                                            const MlsLane& m, float4 mom[MLS_NODES], int& err) {
+#pragma unroll
+    for (int s = 0; s < MLS_NODES; ++s) {
+        mom[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (!m.active[s]) continue;
+        const long long l = win_index(J, P.mdesc[b], m.gx[s], m.gy[s], m.gz[s]);
+        if (l < 0) err |= FLAG_WINDOW;
+        else mom[s] = P.mwin[B.win_off + l];
+    }
 }
 
 __device__ __forceinline__ void load3(const double* p, double v[3]) { v[0] = p[0]; v[1] = p[1]; v[2] = p[2]; }
@@ -353,16 +381,12 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
         }
         MlsLane m;
         mls_setup(J, cen, B.rw, lane, m, err);
-        float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (m.active) {
-            const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
-            if (l < 0) err |= FLAG_WINDOW;
-            else mom = P.mwin[B.win_off + l];
-        }
+        float4 mom[MLS_NODES];
+        mls_moments(P, J, B, b, m, mom, err);
         mls_solve(m, B.alpha, false, err);
-        const double U0 = gsum(m.phi * (double)mom.y);
-        const double U1 = gsum(m.phi * (double)mom.z);
-        const double U2 = gsum(m.phi * (double)mom.w);
+        const double U0 = gsum(m.phi[0] * (double)mom[0].y + m.phi[1] * (double)mom[1].y);
+        const double U1 = gsum(m.phi[0] * (double)mom[0].z + m.phi[1] * (double)mom[1].z);
+        const double U2 = gsum(m.phi[0] * (double)mom[0].w + m.phi[1] * (double)mom[1].w);
         // desired boundary velocity U_b (Sec. 1.2): membranes average their vertex velocities,
         // rigid bodies move the marker with the body
         if (B.rigid) {
@@ -371,18 +395,20 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
             for (int a = 0; a < 3; ++a) Ub[a] = S.u[a] + w[a];
         }
         // F_l = (U_b - U*) / dt, spread with c_l = A_l h (Eq. bodyforce)
-        if (m.active) {
-            const double sc = A * B.shell_h * m.phi;
-            const long long l = win_index(J, fd, m.gx, m.gy, m.gz);
+        const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+#pragma unroll
+        for (int sn = 0; sn < MLS_NODES; ++sn) {
+            if (!m.active[sn]) continue;
+            const double sc = A * B.shell_h * m.phi[sn];
+            const long long l = win_index(J, fd, m.gx[sn], m.gy[sn], m.gz[sn]);
             if (l < 0) {
                 err |= FLAG_WINDOW;
-            } else {
-                const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
-                unsigned long long* fw = (unsigned long long*)(P.fwin + 3 * B.win_off + l);
-                atomicAdd(fw, (unsigned long long)__double2ll_rn(sc * (Ub[0] - U0) * FIX_SCALE));
-                atomicAdd(fw + capn, (unsigned long long)__double2ll_rn(sc * (Ub[1] - U1) * FIX_SCALE));
-                atomicAdd(fw + 2 * capn, (unsigned long long)__double2ll_rn(sc * (Ub[2] - U2) * FIX_SCALE));
+                continue;
             }
+            unsigned long long* fw = (unsigned long long*)(P.fwin + 3 * B.win_off + l);
+            atomicAdd(fw, (unsigned long long)__double2ll_rn(sc * (Ub[0] - U0) * FIX_SCALE));
+            atomicAdd(fw + capn, (unsigned long long)__double2ll_rn(sc * (Ub[1] - U1) * FIX_SCALE));
+            atomicAdd(fw + 2 * capn, (unsigned long long)__double2ll_rn(sc * (Ub[2] - U2) * FIX_SCALE));
         }
     }
     if (err) atomicOr(P.flags + B.job, err);
@@ -423,17 +449,19 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
                               cen[2] + sg * B.probe * nrm[2]};
         MlsLane m;
         mls_setup(J, xp, B.rw, lane, m, err);
-        float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (m.active) {
-            const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
-            if (l < 0) err |= FLAG_WINDOW;
-            else mom = P.mwin[B.win_off + l];
-        }
+        float4 mom[MLS_NODES];
+        mls_moments(P, J, B, b, m, mom, err);
         mls_solve(m, B.alpha, true, err);
-        const double v[10] = {gsum(m.phi * (double)mom.x),
-                              gsum(m.gr[0] * (double)mom.y), gsum(m.gr[1] * (double)mom.y), gsum(m.gr[2] * (double)mom.y),
-                              gsum(m.gr[0] * (double)mom.z), gsum(m.gr[1] * (double)mom.z), gsum(m.gr[2] * (double)mom.z),
-                              gsum(m.gr[0] * (double)mom.w), gsum(m.gr[1] * (double)mom.w), gsum(m.gr[2] * (double)mom.w)};
+        // interpolated rho - 1 and the gradient rows of u* (diffuse derivatives)
+        double loc[10];
+        loc[0] = m.phi[0] * (double)mom[0].x + m.phi[1] * (double)mom[1].x;
+        for (int j = 0; j < 3; ++j) {
+            loc[1 + j] = m.gr[0][j] * (double)mom[0].y + m.gr[1][j] * (double)mom[1].y;
+            loc[4 + j] = m.gr[0][j] * (double)mom[0].z + m.gr[1][j] * (double)mom[1].z;
+            loc[7 + j] = m.gr[0][j] * (double)mom[0].w + m.gr[1][j] * (double)mom[1].w;
+        }
+        double v[10];
+        for (int q = 0; q < 10; ++q) v[q] = gsum(loc[q]);
         if (lane == 0)
             for (int i = 0; i < 10; ++i) probe[grp][i] = v[i];
     }
@@ -560,14 +588,10 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         // membranes: stencil of the vertex and its moments first, so the load overlaps the
         // force gathers below
         MlsLane m;
-        float4 mom = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 mom[MLS_NODES] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
         if (!B.rigid) {
             mls_setup(J, x, B.rw, lane, m, err);
-            if (m.active) {
-                const long long l = win_index(J, P.mdesc[b], m.gx, m.gy, m.gz);
-                if (l < 0) err |= FLAG_WINDOW;
-                else mom = P.mwin[B.win_off + l];
-            }
+            mls_moments(P, J, B, b, m, mom, err);
         }
         // gathered forces: a third of each incident triangle's probe force, its volume force,
         // the spring and bending forces of every incident hinge; lane j takes entry j
@@ -594,8 +618,9 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         if (!B.rigid) {
             // tentative velocity: fluid velocity at the vertex from f^{n+1}
             mls_solve(m, B.alpha, false, err);
-            const double u0[3] = {gsum(m.phi * (double)mom.y), gsum(m.phi * (double)mom.z),
-                                  gsum(m.phi * (double)mom.w)};
+            const double u0[3] = {gsum(m.phi[0] * (double)mom[0].y + m.phi[1] * (double)mom[1].y),
+                                  gsum(m.phi[0] * (double)mom[0].z + m.phi[1] * (double)mom[1].z),
+                                  gsum(m.phi[0] * (double)mom[0].w + m.phi[1] * (double)mom[1].w)};
             const double Fv[3] = {F0, F1, F2};
             double un[3];
             for (int a = 0; a < 3; ++a) {

@@ -19,8 +19,8 @@ constexpr int Q = 19;
 constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
 constexpr double FIX_INV = 1.0 / 1099511627776.0;
 constexpr int WIN_MARGIN = 4;    // nodes around a body's bounding box (probe + support + slack)
-constexpr int GROUP = 32;        // lanes that evaluate one MLS point
-constexpr int MLS_PER_BLOCK = 8; // MLS points (32-lane groups) per 256-thread block
+constexpr int GROUP = 16;         // lanes that evaluate one MLS point (one DPP row)
+constexpr int MLS_PER_BLOCK = 16; // MLS points (16-lane groups) per 256-thread block
 constexpr int MAX_RED_BLOCKS = 65536;
 // window-moments blocks per body: one 256-thread block per this many nodes of window capacity
 constexpr int WIN_NODES_PER_BLOCK = 2048;
@@ -200,6 +200,6 @@ constexpr int WINDOW_KERNEL_MIN_BODIES = 2;
 void launch_triangles(const Pools& P, int nblocks, hipStream_t s);
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s);
 void launch_body_totals(const Pools& P, int body, double* out6, hipStream_t s);
-constexpr int TRI_PER_BLOCK = 4;  // probe kernel: two 32-lane groups (+/- probe) per triangle
+constexpr int TRI_PER_BLOCK = 8;  // probe kernel: two 16-lane groups (+/- probe) per triangle
 
 }  // namespace lbib
