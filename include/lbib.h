@@ -164,10 +164,14 @@ lbib_status lbib_body_get_forces(lbib_lattice* lat, int32_t body, double* f_vert
                                  double M[3]);
 lbib_status lbib_body_count(const lbib_lattice* lat, int32_t body, int32_t* nv, int32_t* nt);
 
-/* Kernel timing with HIP events recorded on the lattice's stream around every launch of the
- * collide+stream sweep (kernel 0) and of the whole step (kernel 1).  Enable before stepping;
- * lbib_kernel_time synchronises and returns the summed milliseconds and launch count since
- * the last reset. */
+/* Kernel timing.  enable = 0 turns it off; enable = n >= 1 stamps start/end events from the
+ * dispatch packet of every n-th launch of the collide+stream sweep (kernel 0; n = 1 times
+ * every launch, a larger n samples the launches evenly and keeps the events' own cost out of
+ * the other steps) and brackets each lbib_step call with events on the lattice's stream
+ * (kernel 1, count = steps).  Timing turns graph replay off.  Enable before stepping;
+ * lbib_kernel_time synchronises and returns the summed milliseconds and the count of timed
+ * launches since the last enable.  Negative enable and kernel ids other than 0 and 1 give
+ * LBIB_EINVAL. */
 lbib_status lbib_set_timing(lbib_lattice* lat, int32_t enable);
 lbib_status lbib_kernel_time(lbib_lattice* lat, int32_t kernel, double* total_ms, int64_t* count);
 

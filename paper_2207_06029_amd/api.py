@@ -157,8 +157,9 @@ class Lattice:
         return fv.reshape(nv, 3), F, M
 
     # timing
-    def set_timing(self, enable: bool):
-        L.check(self._lib.lbib_set_timing(self._h, int(bool(enable))))
+    def set_timing(self, enable=True):
+        """enable: False / 0 off; True / 1 every sweep launch; n > 1 every n-th launch."""
+        L.check(self._lib.lbib_set_timing(self._h, int(enable)))
 
     def kernel_time(self, kernel: int = 0):
         ms = ctypes.c_double()

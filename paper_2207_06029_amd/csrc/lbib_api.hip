@@ -273,8 +273,11 @@ lbib_status lbib_set_timing(lbib_lattice* lat, int32_t enable) {
     lbib_status st = check_handle(lat);
     if (st) return st;
     hipStreamSynchronize(lat->batch->stream);
+    if (enable < 0) return fail(LBIB_EINVAL, "timing period must be >= 0");
     lat->batch->clear_events();
     lat->batch->timing = enable != 0;
+    lat->batch->timing_period = enable > 0 ? enable : 1;
+    lat->batch->sweep_seq = 0;
     return LBIB_OK;
 }
 

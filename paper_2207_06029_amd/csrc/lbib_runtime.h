@@ -76,6 +76,8 @@ struct Batch {
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t capture_stream = nullptr;
     bool timing = false;
+    int timing_period = 1;               // events on every timing_period-th sweep launch
+    long long sweep_seq = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_events, step_events;
     std::vector<hipEvent_t> event_pool;   // created once, reused across timing windows
     size_t event_next = 0;

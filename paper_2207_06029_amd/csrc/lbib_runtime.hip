@@ -713,7 +713,7 @@ lbib_status Batch::enqueue_step(bool collide) {
     const bool bodies = collide && nbodies > 0;
     const bool fold_once = nbodies >= WINDOW_KERNEL_MIN_BODIES;
     if (bodies) launch_centroids(P, nblk_c, nblk_e, !fold_once, stream);
-    if (timing) {
+    if (timing && sweep_seq++ % timing_period == 0) {
         hipEvent_t a, b;
         lbib_status st = next_event(&a);
         if (!st) st = next_event(&b);
