@@ -48,18 +48,18 @@ __device__ __forceinline__ double agent_load(const double* p) {
 
 // One MLS point, per lane of its 16-lane group: lane k owns nodes k and k + 16 (when < 27) of
 // the 3x3x3 block around the nearest node.  mls_setup finds each node, its offset d = x_k - x,
-// r = |d| / r_w and whether it supports the point (r <= 1); the caller then issues its field
-// loads, and mls_solve builds and solves the moment system while those loads are in flight.
+// |d|^2 and whether it supports the point (|d| <= r_w); the caller then issues its field loads,
+// and mls_solve builds and solves the moment system while those loads are in flight.
 constexpr int MLS_NODES = 2;   // stencil nodes per lane
 struct MlsLane {
     bool active[MLS_NODES];
     int gx[MLS_NODES], gy[MLS_NODES], gz[MLS_NODES];
-    double d0[MLS_NODES], d1[MLS_NODES], d2[MLS_NODES], r[MLS_NODES];
+    double d0[MLS_NODES], d1[MLS_NODES], d2[MLS_NODES], r2[MLS_NODES];
     double phi[MLS_NODES];
     double gr[MLS_NODES][3];
 };
 
-__device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], double rw, int lane,
+__device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], double rw2, int lane,
                                           MlsLane& m, int& err) {
     const int c0 = (int)floor(xp[0] + 0.5), c1 = (int)floor(xp[1] + 0.5), c2 = (int)floor(xp[2] + 0.5);
     const int dims[3] = {J.nx, J.ny, J.nz};
@@ -68,7 +68,7 @@ __device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], d
         const int k = lane + GROUP * s;
         m.active[s] = false;
         m.d0[s] = m.d1[s] = m.d2[s] = 0.0;
-        m.r[s] = 2.0;
+        m.r2[s] = 4.0 * rw2;
         m.gr[s][0] = m.gr[s][1] = m.gr[s][2] = 0.0;
         m.gx[s] = m.gy[s] = m.gz[s] = 0;
         if (k >= 27) continue;
@@ -76,8 +76,8 @@ __device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], d
         m.d0[s] = nn[0] - xp[0];
         m.d1[s] = nn[1] - xp[1];
         m.d2[s] = nn[2] - xp[2];
-        m.r[s] = sqrt(m.d0[s] * m.d0[s] + m.d1[s] * m.d1[s] + m.d2[s] * m.d2[s]) / rw;
-        m.active[s] = m.r[s] <= 1.0;
+        m.r2[s] = m.d0[s] * m.d0[s] + m.d1[s] * m.d1[s] + m.d2[s] * m.d2[s];
+        m.active[s] = m.r2[s] <= rw2;
         for (int a = 0; a < 3; ++a) {
             const int bc = J.bc[2 * a];
             if (bc == 0) {
@@ -95,18 +95,24 @@ __device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], d
     }
 }
 
+// 1/x in FP64: hardware reciprocal refined by two Newton steps (x > 0, normal).
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
 // Shape functions phi_k = [A^{-1} W_k p_k]_0 and (optionally) their gradients, A = sum W p p^T,
-// p = (1, d), W = exp(-(r/alpha)^2) (Eqs. l2norm, intKernel).  FP64, Cholesky on every lane.
-__device__ __forceinline__ void mls_solve(MlsLane& m, double alpha, bool want_grad, int& err) {
+// p = (1, d), W = exp(-(|d| / (r_w alpha))^2) (Eqs. l2norm, intKernel).  The weights are
+// evaluated in FP32; the moment matrix is accumulated and factorised (A = L D L^T, unit L) in
+// FP64 on every lane.
+__device__ __forceinline__ void mls_solve(MlsLane& m, float wq, bool want_grad, int& err) {
     double W[MLS_NODES];
     double s00 = 0, s01 = 0, s02 = 0, s03 = 0, s11 = 0, s12 = 0, s13 = 0, s22 = 0, s23 = 0, s33 = 0;
 #pragma unroll
     for (int s = 0; s < MLS_NODES; ++s) {
-        W[s] = 0.0;
-        if (m.active[s]) {
-            const double q = m.r[s] / alpha;
-            W[s] = exp(-q * q);
-        }
+        W[s] = m.active[s] ? (double)expf(-wq * (float)m.r2[s]) : 0.0;
         const double w = W[s], d0 = m.d0[s], d1 = m.d1[s], d2 = m.d2[s];
         s00 += w; s01 += w * d0; s02 += w * d1; s03 += w * d2;
         s11 += w * d0 * d0; s12 += w * d0 * d1; s13 += w * d0 * d2;
@@ -115,26 +121,35 @@ __device__ __forceinline__ void mls_solve(MlsLane& m, double alpha, bool want_gr
     const double a00 = gsum(s00), a01 = gsum(s01), a02 = gsum(s02), a03 = gsum(s03);
     const double a11 = gsum(s11), a12 = gsum(s12), a13 = gsum(s13);
     const double a22 = gsum(s22), a23 = gsum(s23), a33 = gsum(s33);
-    // Cholesky A = L L^T with reciprocal diagonals
-    const double l00 = sqrt(a00), i00 = 1.0 / l00;
-    const double l10 = a01 * i00, l20 = a02 * i00, l30 = a03 * i00;
-    const double l11 = sqrt(a11 - l10 * l10), i11 = 1.0 / l11;
-    const double l21 = (a12 - l20 * l10) * i11, l31 = (a13 - l30 * l10) * i11;
-    const double l22 = sqrt(a22 - l20 * l20 - l21 * l21), i22 = 1.0 / l22;
-    const double l32 = (a23 - l30 * l20 - l31 * l21) * i22;
-    const double l33 = sqrt(a33 - l30 * l30 - l31 * l31 - l32 * l32), i33 = 1.0 / l33;
-    if (!(l33 > 0.0) || !(l22 > 0.0) || !(l11 > 0.0) || !(l00 > 0.0)) err |= FLAG_NONFINITE;
+    // A = L D L^T
+    const double e0 = a00;
+    if (!(e0 > 0.0)) err |= FLAG_NONFINITE;
+    const double i0 = rcp64(e0);
+    const double l10 = a01 * i0, l20 = a02 * i0, l30 = a03 * i0;
+    const double e1 = a11 - l10 * a01;
+    if (!(e1 > 0.0)) err |= FLAG_NONFINITE;
+    const double i1 = rcp64(e1);
+    const double b21 = a12 - l20 * a01, b31 = a13 - l30 * a01;   // D-scaled column entries
+    const double l21 = b21 * i1, l31 = b31 * i1;
+    const double e2 = a22 - l20 * a02 - l21 * b21;
+    if (!(e2 > 0.0)) err |= FLAG_NONFINITE;
+    const double i2 = rcp64(e2);
+    const double b32 = a23 - l30 * a02 - l31 * b21;
+    const double l32 = b32 * i2;
+    const double e3 = a33 - l30 * a03 - l31 * b31 - l32 * b32;
+    if (!(e3 > 0.0)) err |= FLAG_NONFINITE;
+    const double i3 = rcp64(e3);
 #pragma unroll
     for (int s = 0; s < MLS_NODES; ++s) {
-        // v = A^{-1} p_k: forward then back substitution
-        const double y0 = i00;
-        const double y1 = (m.d0[s] - l10 * y0) * i11;
-        const double y2 = (m.d1[s] - l20 * y0 - l21 * y1) * i22;
-        const double y3 = (m.d2[s] - l30 * y0 - l31 * y1 - l32 * y2) * i33;
-        const double v3 = y3 * i33;
-        const double v2 = (y2 - l32 * v3) * i22;
-        const double v1 = (y1 - l21 * v2 - l31 * v3) * i11;
-        const double v0 = (y0 - l10 * v1 - l20 * v2 - l30 * v3) * i00;
+        // v = A^{-1} p_k: L y = p, z = D^{-1} y, L^T v = z
+        const double y0 = 1.0;
+        const double y1 = m.d0[s] - l10 * y0;
+        const double y2 = m.d1[s] - l20 * y0 - l21 * y1;
+        const double y3 = m.d2[s] - l30 * y0 - l31 * y1 - l32 * y2;
+        const double v3 = y3 * i3;
+        const double v2 = y2 * i2 - l32 * v3;
+        const double v1 = y1 * i1 - l21 * v2 - l31 * v3;
+        const double v0 = y0 * i0 - l10 * v1 - l20 * v2 - l30 * v3;
         m.phi[s] = W[s] * v0;
         if (want_grad) { m.gr[s][0] = W[s] * v1; m.gr[s][1] = W[s] * v2; m.gr[s][2] = W[s] * v3; }
     }
@@ -380,10 +395,10 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
             Vt = dot3(pa, bc) * (1.0 / 6.0);
         }
         MlsLane m;
-        mls_setup(J, cen, B.rw, lane, m, err);
+        mls_setup(J, cen, B.rw2, lane, m, err);
         float4 mom[MLS_NODES];
         mls_moments(P, J, B, b, m, mom, err);
-        mls_solve(m, B.alpha, false, err);
+        mls_solve(m, B.wq, false, err);
         const double U0 = gsum(m.phi[0] * (double)mom[0].y + m.phi[1] * (double)mom[1].y);
         const double U1 = gsum(m.phi[0] * (double)mom[0].z + m.phi[1] * (double)mom[1].z);
         const double U2 = gsum(m.phi[0] * (double)mom[0].w + m.phi[1] * (double)mom[1].w);
@@ -448,10 +463,10 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
         const double xp[3] = {cen[0] + sg * B.probe * nrm[0], cen[1] + sg * B.probe * nrm[1],
                               cen[2] + sg * B.probe * nrm[2]};
         MlsLane m;
-        mls_setup(J, xp, B.rw, lane, m, err);
+        mls_setup(J, xp, B.rw2, lane, m, err);
         float4 mom[MLS_NODES];
         mls_moments(P, J, B, b, m, mom, err);
-        mls_solve(m, B.alpha, true, err);
+        mls_solve(m, B.wq, true, err);
         // interpolated rho - 1 and the gradient rows of u* (diffuse derivatives)
         double loc[10];
         loc[0] = m.phi[0] * (double)mom[0].x + m.phi[1] * (double)mom[1].x;
@@ -590,7 +605,7 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         MlsLane m;
         float4 mom[MLS_NODES] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
         if (!B.rigid) {
-            mls_setup(J, x, B.rw, lane, m, err);
+            mls_setup(J, x, B.rw2, lane, m, err);
             mls_moments(P, J, B, b, m, mom, err);
         }
         // gathered forces: a third of each incident triangle's probe force, its volume force,
@@ -617,7 +632,7 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         const double F0 = gsum(f[0]), F1 = gsum(f[1]), F2 = gsum(f[2]);
         if (!B.rigid) {
             // tentative velocity: fluid velocity at the vertex from f^{n+1}
-            mls_solve(m, B.alpha, false, err);
+            mls_solve(m, B.wq, false, err);
             const double u0[3] = {gsum(m.phi[0] * (double)mom[0].y + m.phi[1] * (double)mom[1].y),
                                   gsum(m.phi[0] * (double)mom[0].z + m.phi[1] * (double)mom[1].z),
                                   gsum(m.phi[0] * (double)mom[0].w + m.phi[1] * (double)mom[1].w)};

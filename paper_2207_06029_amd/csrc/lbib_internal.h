@@ -116,6 +116,8 @@ struct BodyDev {
     int blk_c0, nblk_c, blk_e0, nblk_e, blk_t0, nblk_t, blk_v0, nblk_v, blk_w0, nblk_w;
     double kb, kv, mv, V0, mass;
     double rw, alpha, probe, shell_h;
+    double rw2;                 // r_w^2: support test on squared distances
+    float wq;                   // 1 / (r_w alpha)^2: weight W = exp(-wq |d|^2)
     double gravity[3];
     double Ib[9];               // rigid inertia in the rest frame (about the centroid)
 };

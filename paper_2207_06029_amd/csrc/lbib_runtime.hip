@@ -456,6 +456,8 @@ lbib_status Batch::rebuild_bodies() {
         }
         B.kb = h.desc.kb; B.kv = h.desc.kv; B.mv = h.mv; B.V0 = h.V0; B.mass = h.mass;
         B.rw = h.desc.mls_rw; B.alpha = h.desc.mls_alpha; B.probe = h.desc.probe_len; B.shell_h = h.desc.shell_h;
+        B.rw2 = h.desc.mls_rw * h.desc.mls_rw;
+        B.wq = (float)(1.0 / (B.rw2 * h.desc.mls_alpha * h.desc.mls_alpha));
         for (int a = 0; a < 3; ++a) B.gravity[a] = h.desc.gravity[a];
         for (int k = 0; k < 9; ++k) B.Ib[k] = h.Ib[k];
         const int dims[3] = {J.nx, J.ny, J.nz};
