@@ -133,3 +133,22 @@ def test_errors_surface(api):
     with pytest.raises(api.L.LbibError) as ei:
         lat.body_state(3)
     assert ei.value.code == -6
+    # invalid timing requests are rejected; a sampling period times every n-th sweep launch
+    with pytest.raises(api.L.LbibError) as ei:
+        lat.set_timing(-1)
+    assert ei.value.code == -1
+    with pytest.raises(api.L.LbibError) as ei:
+        lat.kernel_time(2)
+    assert ei.value.code == -1
+    lat.set_timing(4)
+    lat.step(10)
+    ms, n = lat.kernel_time(0)
+    assert n == 3 and ms > 0.0           # launches 0, 4 and 8 of the 10
+    ms, n = lat.kernel_time(1)
+    assert n == 10
+    lat.set_timing(0)
+    # an unknown vertex-update mode is refused at upload
+    xyz, tri = I.spheroid_mesh(1, (2.0, 2.0, 2.0), (3.5, 3.5, 3.5))
+    with pytest.raises(api.L.LbibError) as ei:
+        lat.add_body(I.BodySpec(rigid=0, ks0=0.01, kb=0.0, kv=0.0, mass_ratio=1.0, integrator=3), xyz, tri)
+    assert ei.value.code == -1
