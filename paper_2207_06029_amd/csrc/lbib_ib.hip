@@ -181,6 +181,19 @@ __device__ __forceinline__ void mls_moments(const Pools& P, const JobDev& J, con
     }
 }
 
+// sum_k c_k q_k over the group for per-node coefficients c (phi or a gradient row) and field
+// values q (component `comp` of the moments: 0 rho - 1, 1..3 u*)
+__device__ __forceinline__ double group_dot(const double* c, int cstride, const float4 mom[MLS_NODES],
+                                            int comp) {
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < MLS_NODES; ++s) {
+        const float q = comp == 0 ? mom[s].x : (comp == 1 ? mom[s].y : (comp == 2 ? mom[s].z : mom[s].w));
+        acc += c[s * cstride] * (double)q;
+    }
+    return gsum(acc);
+}
+
 __device__ __forceinline__ void load3(const double* p, double v[3]) { v[0] = p[0]; v[1] = p[1]; v[2] = p[2]; }
 __device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3]) {
     c[0] = a[1] * b[2] - a[2] * b[1];
@@ -399,9 +412,9 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
         float4 mom[MLS_NODES];
         mls_moments(P, J, B, b, m, mom, err);
         mls_solve(m, B.wq, false, err);
-        const double U0 = gsum(m.phi[0] * (double)mom[0].y + m.phi[1] * (double)mom[1].y);
-        const double U1 = gsum(m.phi[0] * (double)mom[0].z + m.phi[1] * (double)mom[1].z);
-        const double U2 = gsum(m.phi[0] * (double)mom[0].w + m.phi[1] * (double)mom[1].w);
+        const double U0 = group_dot(m.phi, 1, mom, 1);
+        const double U1 = group_dot(m.phi, 1, mom, 2);
+        const double U2 = group_dot(m.phi, 1, mom, 3);
         // desired boundary velocity U_b (Sec. 1.2): membranes average their vertex velocities,
         // rigid bodies move the marker with the body
         if (B.rigid) {
@@ -468,15 +481,13 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P) {
         mls_moments(P, J, B, b, m, mom, err);
         mls_solve(m, B.wq, true, err);
         // interpolated rho - 1 and the gradient rows of u* (diffuse derivatives)
-        double loc[10];
-        loc[0] = m.phi[0] * (double)mom[0].x + m.phi[1] * (double)mom[1].x;
-        for (int j = 0; j < 3; ++j) {
-            loc[1 + j] = m.gr[0][j] * (double)mom[0].y + m.gr[1][j] * (double)mom[1].y;
-            loc[4 + j] = m.gr[0][j] * (double)mom[0].z + m.gr[1][j] * (double)mom[1].z;
-            loc[7 + j] = m.gr[0][j] * (double)mom[0].w + m.gr[1][j] * (double)mom[1].w;
-        }
         double v[10];
-        for (int q = 0; q < 10; ++q) v[q] = gsum(loc[q]);
+        v[0] = group_dot(m.phi, 1, mom, 0);
+        for (int j = 0; j < 3; ++j) {
+            v[1 + j] = group_dot(&m.gr[0][j], 3, mom, 1);
+            v[4 + j] = group_dot(&m.gr[0][j], 3, mom, 2);
+            v[7 + j] = group_dot(&m.gr[0][j], 3, mom, 3);
+        }
         if (lane == 0)
             for (int i = 0; i < 10; ++i) probe[grp][i] = v[i];
     }
@@ -603,7 +614,9 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         // membranes: stencil of the vertex and its moments first, so the load overlaps the
         // force gathers below
         MlsLane m;
-        float4 mom[MLS_NODES] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+        float4 mom[MLS_NODES];
+#pragma unroll
+        for (int sn = 0; sn < MLS_NODES; ++sn) mom[sn] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (!B.rigid) {
             mls_setup(J, x, B.rw2, lane, m, err);
             mls_moments(P, J, B, b, m, mom, err);
@@ -633,9 +646,8 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         if (!B.rigid) {
             // tentative velocity: fluid velocity at the vertex from f^{n+1}
             mls_solve(m, B.wq, false, err);
-            const double u0[3] = {gsum(m.phi[0] * (double)mom[0].y + m.phi[1] * (double)mom[1].y),
-                                  gsum(m.phi[0] * (double)mom[0].z + m.phi[1] * (double)mom[1].z),
-                                  gsum(m.phi[0] * (double)mom[0].w + m.phi[1] * (double)mom[1].w)};
+            const double u0[3] = {group_dot(m.phi, 1, mom, 1), group_dot(m.phi, 1, mom, 2),
+                                  group_dot(m.phi, 1, mom, 3)};
             const double Fv[3] = {F0, F1, F2};
             double un[3];
             for (int a = 0; a < 3; ++a) {
