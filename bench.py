@@ -37,12 +37,12 @@ PEAK_HBM_GBS = 8000.0
 TIMING_PERIOD = 10
 SWEEP_SOURCES = ("paper_2207_06029_amd/csrc/lbib_lattice.hip", "paper_2207_06029_amd/csrc/lbib_internal.h")
 SWEEP_TRAFFIC = {
-    # FETCH_SIZE 39,413.9 KiB x 2.0 + WRITE_SIZE 77,824 KiB x 1.0 per dispatch
-    "prolate128": {"sha256": "55adf07de18f3ac00b687592ae72a8429a2a91b5f60696fe2288f70d8ae1d8b5",
-                   "bytes": 160411443},
-    # FETCH_SIZE 313,574.1 KiB x 2.0 + WRITE_SIZE 622,592 KiB x 1.0 per dispatch
-    "prolate256": {"sha256": "55adf07de18f3ac00b687592ae72a8429a2a91b5f60696fe2288f70d8ae1d8b5",
-                   "bytes": 1279733965},
+    # FETCH_SIZE 39,414.3 KiB x 2.0 + WRITE_SIZE 77,824.1 KiB x 1.0 per dispatch
+    "prolate128": {"sha256": "60f675167c0f60d0ebd137ebb20aba88eb5625934dd1c1652aa6863a895022d4",
+                   "bytes": 160412365},
+    # FETCH_SIZE 313,575.9 KiB x 2.0 + WRITE_SIZE 622,592.0 KiB x 1.0 per dispatch
+    "prolate256": {"sha256": "60f675167c0f60d0ebd137ebb20aba88eb5625934dd1c1652aa6863a895022d4",
+                   "bytes": 1279737651},
 }
 
 
