@@ -75,8 +75,14 @@ lbib_status autotune(Batch& B, const char* cache) {
     const SweepShape cand[] = {{128, 1}, {256, 1}, {512, 1}, {1024, 1}, {256, 2}, {512, 2}, {256, 4}};
     SweepShape best = B.shape;
     double best_ms = 1e30;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    struct Events {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    if (hipEventCreate(&ev.e0) != hipSuccess || hipEventCreate(&ev.e1) != hipSuccess)
         return fail(LBIB_EDEVICE, "event create failed");
     for (const SweepShape& c : cand) {
         lbib_status st = B.set_shape(c);
@@ -84,18 +90,16 @@ lbib_status autotune(Batch& B, const char* cache) {
         // sweeps from the current buffer into the other one; the state is not advanced
         for (int w = 0; w < 2; ++w)
             launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tile_job.size(), c, B.stream);
-        hipEventRecord(e0, B.stream);
+        if (hipEventRecord(ev.e0, B.stream) != hipSuccess) return fail(LBIB_EDEVICE, "autotune event record failed");
         const int reps = 8;
         for (int r = 0; r < reps; ++r)
             launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tile_job.size(), c, B.stream);
-        hipEventRecord(e1, B.stream);
-        if (hipEventSynchronize(e1) != hipSuccess) return fail(LBIB_EDEVICE, "autotune sync failed");
+        if (hipEventRecord(ev.e1, B.stream) != hipSuccess) return fail(LBIB_EDEVICE, "autotune event record failed");
+        if (hipEventSynchronize(ev.e1) != hipSuccess) return fail(LBIB_EDEVICE, "autotune sync failed");
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess) return fail(LBIB_EDEVICE, "autotune timing failed");
         if (ms < best_ms) { best_ms = ms; best = c; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     if (cache) {
         table[key] = best;
         std::ofstream out(cache);
@@ -272,8 +276,9 @@ lbib_status lbib_body_count(const lbib_lattice* lat, int32_t body, int32_t* nv, 
 lbib_status lbib_set_timing(lbib_lattice* lat, int32_t enable) {
     lbib_status st = check_handle(lat);
     if (st) return st;
-    hipStreamSynchronize(lat->batch->stream);
     if (enable < 0) return fail(LBIB_EINVAL, "timing period must be >= 0");
+    if (hipStreamSynchronize(lat->batch->stream) != hipSuccess)
+        return fail(LBIB_EDEVICE, "stream synchronisation failed");
     lat->batch->clear_events();
     lat->batch->timing = enable != 0;
     lat->batch->timing_period = enable > 0 ? enable : 1;

@@ -64,7 +64,6 @@ struct Batch {
     std::vector<BodyDev> host_bodies;
     int nbodies = 0;
     int nblk_c = 0, nblk_e = 0, nblk_t = 0, nblk_v = 0, nblk_w = 0;
-    long long max_cap = 0, max_red = 0;
     Pools P{};
     bool cur_b = false;        // buffer holding the latest post-collision state
     bool primed = false;       // moment windows hold the moments of the current state

@@ -27,6 +27,19 @@ const char* last_error() { return g_err.c_str(); }
         if (e_ != hipSuccess) return fail(LBIB_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+// Temporary device buffer of one host call, released on every return path.
+template <typename T>
+struct DevTemp {
+    T* p = nullptr;
+    hipError_t alloc(size_t count) { return hipMalloc(&p, sizeof(T) * (count > 0 ? count : 1)); }
+    DevTemp() = default;
+    DevTemp(const DevTemp&) = delete;
+    DevTemp& operator=(const DevTemp&) = delete;
+    ~DevTemp() {
+        if (p) (void)hipFree(p);
+    }
+};
+
 // ---------------------------------------------------------------- device allocation
 lbib_status Arena::alloc(size_t bytes, void** out) {
     bytes = (bytes + 255) & ~size_t(255);
@@ -48,13 +61,13 @@ lbib_status Arena::alloc(size_t bytes, void** out) {
 void Arena::release_from(size_t mark_used, size_t mark_owned) {
     if (base) { used = mark_used; return; }
     while (owned.size() > mark_owned) {
-        hipFree(owned.back());
+        (void)hipFree(owned.back());
         owned.pop_back();
     }
 }
 Arena::~Arena() {
     if (!base)
-        for (void* p : owned) hipFree(p);
+        for (void* p : owned) (void)hipFree(p);
 }
 
 template <typename T>
@@ -387,8 +400,8 @@ lbib_status Batch::retile() {
     }
     HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, stream));
     if (d_tile_job && tile_cap < tile_job.size()) {
-        hipStreamSynchronize(stream);
-        hipFree(d_tile_job);
+        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipFree(d_tile_job));
         d_tile_job = nullptr;
     }
     if (!d_tile_job) {
@@ -422,7 +435,6 @@ lbib_status Batch::rebuild_bodies() {
     std::vector<WinDesc> fd(hbodies.size());
     std::vector<BodyState> bs(hbodies.size());
     long long v0 = 0, t0 = 0, e0 = 0, woff = 0, red = 0;
-    max_cap = 0;
     nblk_c = nblk_e = nblk_t = nblk_v = nblk_w = 0;
     for (size_t i = 0; i < hbodies.size(); ++i) {
         HostBody& h = hbodies[i];
@@ -465,7 +477,6 @@ lbib_status Batch::rebuild_bodies() {
         const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
         B.win_off = woff;
         woff += capn;
-        max_cap = std::max<long long>(max_cap, capn);
         const int nbc = (h.nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
         const int nbt = (h.nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
         const int nbv = (h.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
@@ -517,7 +528,6 @@ lbib_status Batch::rebuild_bodies() {
         if (over) return fail(LBIB_EDOMAIN, "body does not fit its window");
     }
     nbodies = (int)hbodies.size();
-    max_red = red;
     if ((st = upload(arena, bd, (BodyDev**)&P.bodies, stream))) return st;
     if ((st = upload(arena, bc, (int**)&P.blk_body_c, stream))) return st;
     if ((st = upload(arena, be, (int**)&P.blk_body_e, stream))) return st;
@@ -623,17 +633,20 @@ int Batch::body_index(int job, int local) const {
 // ---------------------------------------------------------------- state
 lbib_status Batch::init_job(int job, const double* rho, const double* u) {
     const long long n = jobs[job].n;
-    double *drho = nullptr, *du = nullptr, *df = nullptr;
-    if (rho) { HIP_TRY(hipMalloc(&drho, sizeof(double) * n)); HIP_TRY(hipMemcpyAsync(drho, rho, sizeof(double) * n, hipMemcpyHostToDevice, stream)); }
-    if (u) { HIP_TRY(hipMalloc(&du, sizeof(double) * 3 * n)); HIP_TRY(hipMemcpyAsync(du, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, stream)); }
-    HIP_TRY(hipMalloc(&df, sizeof(double) * 19 * n));
-    launch_init_eq(job, n, drho, du, df, stream);
-    launch_set_pops(P, storage, cur_b, job, n, df, stream);
+    DevTemp<double> drho, du, df;
+    if (rho) {
+        HIP_TRY(drho.alloc(n));
+        HIP_TRY(hipMemcpyAsync(drho.p, rho, sizeof(double) * n, hipMemcpyHostToDevice, stream));
+    }
+    if (u) {
+        HIP_TRY(du.alloc(3 * n));
+        HIP_TRY(hipMemcpyAsync(du.p, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, stream));
+    }
+    HIP_TRY(df.alloc(19 * n));
+    launch_init_eq(job, n, drho.p, du.p, df.p, stream);
+    launch_set_pops(P, storage, cur_b, job, n, df.p, stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(stream));
-    hipFree(df);
-    if (drho) hipFree(drho);
-    if (du) hipFree(du);
     primed = false;
     step_count = 0;
     return LBIB_OK;
@@ -641,13 +654,12 @@ lbib_status Batch::init_job(int job, const double* rho, const double* u) {
 
 lbib_status Batch::set_populations(int job, const double* f) {
     const long long n = jobs[job].n;
-    double* df = nullptr;
-    HIP_TRY(hipMalloc(&df, sizeof(double) * 19 * n));
-    HIP_TRY(hipMemcpyAsync(df, f, sizeof(double) * 19 * n, hipMemcpyHostToDevice, stream));
-    launch_set_pops(P, storage, cur_b, job, n, df, stream);
+    DevTemp<double> df;
+    HIP_TRY(df.alloc(19 * n));
+    HIP_TRY(hipMemcpyAsync(df.p, f, sizeof(double) * 19 * n, hipMemcpyHostToDevice, stream));
+    launch_set_pops(P, storage, cur_b, job, n, df.p, stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(stream));
-    hipFree(df);
     primed = false;
     return LBIB_OK;
 }
@@ -673,14 +685,13 @@ lbib_status Batch::job_flags(std::vector<int>& fl) {
 
 lbib_status Batch::get_macros(int job, double* rho, double* u) {
     const long long n = jobs[job].n;
-    float* d = nullptr;
-    HIP_TRY(hipMalloc(&d, sizeof(float) * 4 * n));
-    launch_macros(P, storage, cur_b, job, n, d, stream);
+    DevTemp<float> d;
+    HIP_TRY(d.alloc(4 * n));
+    launch_macros(P, storage, cur_b, job, n, d.p, stream);
     HIP_TRY(hipGetLastError());
     std::vector<float> h(4 * n);
-    HIP_TRY(hipMemcpyAsync(h.data(), d, sizeof(float) * 4 * n, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(h.data(), d.p, sizeof(float) * 4 * n, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    hipFree(d);
     for (long long k = 0; k < n; ++k) {
         if (rho) rho[k] = 1.0 + (double)h[4 * k];
         if (u) for (int a = 0; a < 3; ++a) u[a * n + k] = (double)h[4 * k + 1 + a];
@@ -690,14 +701,13 @@ lbib_status Batch::get_macros(int job, double* rho, double* u) {
 
 lbib_status Batch::get_populations(int job, double* f) {
     const long long n = jobs[job].n;
-    float* d = nullptr;
-    HIP_TRY(hipMalloc(&d, sizeof(float) * 19 * n));
-    launch_get_pops(P, storage, cur_b, job, n, d, stream);
+    DevTemp<float> d;
+    HIP_TRY(d.alloc(19 * n));
+    launch_get_pops(P, storage, cur_b, job, n, d.p, stream);
     HIP_TRY(hipGetLastError());
     std::vector<float> h(19 * n);
-    HIP_TRY(hipMemcpyAsync(h.data(), d, sizeof(float) * 19 * n, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(h.data(), d.p, sizeof(float) * 19 * n, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    hipFree(d);
     for (int i = 0; i < 19; ++i)
         for (long long k = 0; k < n; ++k) f[i * n + k] = wq(i) + (double)h[i * n + k];
     return LBIB_OK;
@@ -773,14 +783,15 @@ lbib_status Batch::step(int nsteps, bool collide) {
 }
 
 lbib_status Batch::capture_graph() {
-    if (graph_exec) { hipGraphExecDestroy(graph_exec); graph_exec = nullptr; }
-    if (graph) { hipGraphDestroy(graph); graph = nullptr; }
+    if (graph_exec) { HIP_TRY(hipGraphExecDestroy(graph_exec)); graph_exec = nullptr; }
+    if (graph) { HIP_TRY(hipGraphDestroy(graph)); graph = nullptr; }
     if (!capture_stream) HIP_TRY(hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking));
     hipStream_t user = stream;
     HIP_TRY(hipStreamSynchronize(user));
+    HIP_TRY(hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal));
+    // launches of the two steps go to the capture stream; the caller's stream is restored below
     stream = capture_stream;
     const bool start_b = cur_b;
-    HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     lbib_status st = enqueue_step(true);
     if (!st) st = enqueue_step(true);
     hipError_t e = hipStreamEndCapture(stream, &graph);
@@ -829,14 +840,15 @@ void Batch::clear_events() {
     step_event_steps = 0;
 }
 
+// Destruction cannot report errors: every release is attempted and its status dropped.
 Batch::~Batch() {
-    if (stream) hipStreamSynchronize(stream);
+    if (stream) (void)hipStreamSynchronize(stream);
     clear_events();
-    for (hipEvent_t e : event_pool) hipEventDestroy(e);
-    if (graph_exec) hipGraphExecDestroy(graph_exec);
-    if (graph) hipGraphDestroy(graph);
-    if (capture_stream) hipStreamDestroy(capture_stream);
-    if (d_tile_job) hipFree(d_tile_job);
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    if (d_tile_job) (void)hipFree(d_tile_job);
 }
 
 // ---------------------------------------------------------------- body state access
@@ -859,13 +871,12 @@ lbib_status Batch::body_forces(int bi, double* fv, double* F, double* M) {
         for (int a = 0; a < 3; ++a) { tot[a] = S.F[a]; tot[3 + a] = S.M[a]; }
     } else {
         // membranes: totals of the last step's probe forces, reduced on the device in FP64
-        double* d = nullptr;
-        HIP_TRY(hipMalloc(&d, sizeof(double) * 6));
-        launch_body_totals(P, bi, d, stream);
+        DevTemp<double> d;
+        HIP_TRY(d.alloc(6));
+        launch_body_totals(P, bi, d.p, stream);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(tot, d, sizeof tot, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(tot, d.p, sizeof tot, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
-        hipFree(d);
     }
     if (F) for (int a = 0; a < 3; ++a) F[a] = tot[a];
     if (M) for (int a = 0; a < 3; ++a) M[a] = tot[3 + a];
