@@ -281,6 +281,8 @@ void orc_lattice_destroy(orc_lattice* L) {
 
 int64_t orc_step_count(const orc_lattice* L) { return L->step; }
 
+/* Density rho = sum f and force-free velocity u* = sum f e / rho of the post-streaming state
+ * (moments of Eq. eqfunc, Sec. 1.1; reading: u* feeds the immersed boundary). */
 static void moments(orc_lattice* L) {
     const long N = L->N;
 #pragma omp parallel for schedule(static) num_threads(g_threads)
@@ -296,8 +298,8 @@ static void moments(orc_lattice* L) {
     }
 }
 
-/* Apply the Zou-He closure to every node on a Zou-He face (the state must satisfy the wall
- * condition at every time level). */
+/* Apply the Zou-He closure (Sec. 1.1) to every node on a Zou-He face (the state must satisfy
+ * the wall condition at every time level). */
 static void close_walls(orc_lattice* L) {
     const long N = L->N;
     for (int a = 0; a < 3; ++a)
@@ -370,7 +372,7 @@ static void collide_all(orc_lattice* L, int with_collision) {
     }
 }
 
-/* Streaming fs -> f: f_i(x) = fs_i(x - e_i) with periodic wrap; a source behind a bounce-back
+/* Streaming part of Eq. (evoleq), fs -> f: f_i(x) = fs_i(x - e_i) with periodic wrap; a source behind a bounce-back
  * wall returns the node's own opposite population plus the moving-wall term; a source behind a
  * Zou-He face is reconstructed by the closure afterwards. */
 static void stream_all(orc_lattice* L) {
@@ -434,7 +436,7 @@ int orc_stream_only(orc_lattice* L, int nsteps) {
 
 /* ------------------------------------------------------------------ MLS (Sec. 1.2) */
 
-/* Valid node range along a walled axis for immersed-boundary support: all nodes behind
+/* Valid node range along a walled axis for the MLS support (Sec. 1.2): all nodes behind
  * halfway bounce-back walls, interior nodes only on a Zou-He axis. */
 static int axis_range(const orc_lattice* L, int a, int* lo, int* hi) {
     int n = dim(L, a);
@@ -445,7 +447,8 @@ static int axis_range(const orc_lattice* L, int a, int* lo, int* hi) {
     return 1;
 }
 
-/* Cholesky factorisation and inverse of the symmetric positive definite 4x4 moment matrix. */
+/* Cholesky factorisation and inverse of the symmetric positive definite 4x4 moment matrix of
+ * the MLS fit (Eq. l2norm, Sec. 1.2). */
 static int spd_inverse4(const double A[16], double Ai[16]) {
     double Lm[16] = {0};
     for (int j = 0; j < 4; ++j) {
@@ -578,6 +581,8 @@ static void tri_geom(const double* x, const int* t, double cen[3], double N[3]) 
     cross(ab, ac, N);
 }
 
+/* Enclosed volume by the divergence theorem, sum over triangles of x_a . (x_b x x_c) / 6: the V of
+ * the volume constraint (Eq. volFor, Sec. 1.3). */
 static double enclosed_volume(const double* x, const int* tri, int nt) {
     double V = 0.0;
     for (int t = 0; t < nt; ++t) {
@@ -589,7 +594,7 @@ static double enclosed_volume(const double* x, const int* tri, int nt) {
     return V;
 }
 
-/* Signed dihedral angle of a hinge: x1, x2 on the shared edge (ordered as in triangle 1),
+/* Signed dihedral angle theta of the bending energy (Eqs. bendPot, bendFor, Sec. 1.3) for a hinge: x1, x2 on the shared edge (ordered as in triangle 1),
  * x3 opposite in triangle 1 (x1,x2,x3), x4 opposite in triangle 2 (x2,x1,x4). */
 static double dihedral(const double* x, const int* h) {
     const double *x1 = x + 3 * h[0], *x2 = x + 3 * h[1], *x3 = x + 3 * h[2], *x4 = x + 3 * h[3];
@@ -614,7 +619,8 @@ static int cmp_edge(const void* p, const void* q) {
     return 0;
 }
 
-/* Solid-polyhedron mass properties (unit density): volume, centroid, second moment about it. */
+/* Solid-polyhedron mass properties (unit density): volume, centroid, second moment about it; they
+ * give the rigid mass and inertia of Eqs. (linearVelRig), (angularVelRig) (Sec. 1.3). */
 static void polyhedron_moments(const double* x, const int* tri, int nt, double* V, double X[3],
                                double C[9]) {
     double v = 0.0, m1[3] = {0, 0, 0};
@@ -645,6 +651,9 @@ static void polyhedron_moments(const double* x, const int* tri, int nt, double* 
     *V = v;
 }
 
+/* Rest state of a body (Sec. 1.3): edges and hinges of the closed mesh, rest lengths and angles,
+ * Van Gelder spring constants k_s,l = k_s0 T (A1 + A2) / l0^2 (after Eq. strainFor), vertex mass
+ * m_v = ratio T S0 / M_v (Eq. newtonSoft), and for rigid bodies mass and inertia. */
 int orc_body_add(orc_lattice* L, const orc_body_desc* d, const double* xyz, int32_t nv,
                  const int32_t* tri, int32_t nt, int32_t* body_id) {
     if (L->nb >= MAXB) { set_err("too many bodies"); return ORC_EINVAL; }
@@ -760,6 +769,8 @@ int orc_body_add(orc_lattice* L, const orc_body_desc* d, const double* xyz, int3
     return ORC_OK;
 }
 
+/* Initial velocity and a consistent history for the multistep updates (reading: the paper leaves
+ * the start-up of Eqs. verletPos / linearVelRig open): x^{-1} = x^0 - v dt, u^{-1} = u^{-2} = v. */
 int orc_body_set_velocity(orc_lattice* L, int32_t id, const double* v) {
     if (id < 0 || id >= L->nb) { set_err("no such body"); return ORC_EINVAL; }
     body_t* b = L->b[id];
@@ -812,7 +823,8 @@ int orc_body_rigid_props(const orc_lattice* L, int32_t id, double X0[3], double*
     return ORC_OK;
 }
 
-/* Vertex velocity of the current state (rigid: u + omega x (x_v - X)). */
+/* Vertex velocity of the current state, the input of the desired boundary velocity U_b (Sec. 1.2;
+ * rigid: u + omega x (x_v - X)). */
 static void vertex_velocity(const body_t* b, int v, double out[3]) {
     if (!b->d.rigid) {
         for (int a = 0; a < 3; ++a) out[a] = b->uv[3 * v + a];
