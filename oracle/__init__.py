@@ -128,6 +128,17 @@ def wall_closure(axis: int, side: int, uw, F, f) -> np.ndarray:
     return f
 
 
+def corner_closure(side, rho: float, uw, F, f) -> np.ndarray:
+    f = np.array(f, dtype=np.float64)
+    sd = np.ascontiguousarray(side, dtype=np.int32)
+    uw = np.ascontiguousarray(uw, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    rc = lib().orc_corner_closure(_p(sd, _I32), ctypes.c_double(rho), _p(uw), _p(F), _p(f))
+    if rc != 0:
+        raise OracleError(rc, "singular corner system")
+    return f
+
+
 def _lattice_desc(spec) -> _LatticeDesc:
     d = _LatticeDesc()
     d.nx, d.ny, d.nz = int(spec.nx), int(spec.ny), int(spec.nz)

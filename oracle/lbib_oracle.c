@@ -32,6 +32,13 @@
  *   - Zou-He momentum target rho u_w - G/2 (G = uniform body force), so the Guo velocity at
  *     a wall node equals the wall velocity; immersed-boundary support may not reach wall nodes.
  *   - the state at every time level (including the initial one) satisfies the wall closure.
+ *   - Zou-He walls on several axes (square duct, closed box): at an edge or a corner the
+ *     populations streamed in through any of the node's walls are rebuilt by bounce-back of the
+ *     non-equilibrium part (links buried in the wall: equilibrium), then corrected by a weighted
+ *     least-squares term to the node's mass and momentum target.  The node's density balances
+ *     its mass through its walls; its wall velocity is zero along its wall normals and the mean
+ *     of its faces' velocities along the other axes.  Such walls must all be Zou-He and move
+ *     tangentially.
  *   - halfway bounce-back walls sit half a spacing outside the first/last node, with the
  *     moving-wall term 2 w_i rho0 (e_i . u_w) / c_s^2, rho0 = 1.
  *   - rigid bodies: mass m = ratio * V0 (fluid density 1), net gravity (m - V0) g, inertia of
@@ -178,6 +185,61 @@ void orc_wall_closure(int axis, int side, const double uw[3], const double F[3],
     }
 }
 
+static int spd_inverse4(const double A[16], double Ai[16]);
+
+/*
+ * Known-velocity closure on a node that lies on two or three Zou-He faces (an edge or a corner
+ * of the box).  The paper names Zou-He walls (Sec. 1.1) without saying how edges and corners are
+ * closed; the reading taken here:
+ *   - unknown populations are those streamed in through any of the node's walls;
+ *   - an unknown whose opposite is known takes that opposite plus the equilibrium difference,
+ *     2 w_i (e_i . m) / c_s^2 (bounce-back of the non-equilibrium part, as on a face);
+ *     an unknown whose opposite is unknown too (a link buried in the wall) takes f_i^eq(rho, u_w);
+ *   - the unknowns are then corrected by w_i (lambda_0 + lambda . e_i), lambda chosen so that the
+ *     node carries exactly the mass rho and the momentum m = rho u_w - F/2 (the weighted
+ *     least-squares correction over the unknowns; on a face it would reproduce the transverse
+ *     terms of the face closure).
+ * The density cannot follow from the known populations on an edge or a corner; the caller
+ * passes it in (the lattice balances the node's mass, see close_edges).
+ * side[a] = -1 low face of axis a, +1 high face, 0 not on a wall of that axis.
+ */
+int orc_corner_closure(const int32_t side[3], double rho, const double uw[3], const double F[3],
+                       double f[19]) {
+    int unk[Q];
+    for (int i = 0; i < Q; ++i) {
+        unk[i] = 0;
+        for (int a = 0; a < 3; ++a)
+            if (side[a] != 0 && E[i][a] == -side[a]) unk[i] = 1;
+    }
+    double m[3], feq[Q];
+    for (int d = 0; d < 3; ++d) m[d] = rho * uw[d] - 0.5 * F[d];
+    orc_equilibrium(rho, uw, feq);
+    for (int i = 0; i < Q; ++i) {
+        if (!unk[i]) continue;
+        const int j = opposite(i);
+        if (unk[j]) f[i] = feq[i];
+        else f[i] = f[j] + 2.0 * weight(i) * (E[i][0] * m[0] + E[i][1] * m[1] + E[i][2] * m[2]) / CS2;
+    }
+    double r[4] = {rho, m[0], m[1], m[2]};
+    double A[16] = {0};
+    for (int i = 0; i < Q; ++i) {
+        r[0] -= f[i];
+        for (int d = 0; d < 3; ++d) r[1 + d] -= f[i] * E[i][d];
+        if (!unk[i]) continue;
+        const double p[4] = {1.0, (double)E[i][0], (double)E[i][1], (double)E[i][2]};
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) A[4 * a + b] += weight(i) * p[a] * p[b];
+    }
+    double Ai[16];
+    if (spd_inverse4(A, Ai) != 0) return -1;
+    double lam[4] = {0, 0, 0, 0};
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) lam[a] += Ai[4 * a + b] * r[b];
+    for (int i = 0; i < Q; ++i)
+        if (unk[i]) f[i] += weight(i) * (lam[0] + lam[1] * E[i][0] + lam[2] * E[i][1] + lam[3] * E[i][2]);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ data */
 
 typedef struct {
@@ -198,6 +260,7 @@ struct orc_lattice {
     long N;
     double tau;
     int bc[6];
+    int zh_axes;          /* axes carrying Zou-He walls */
     double wall_u[6][3];
     double G[3];
     double *f, *fs, *rho, *u, *flb;
@@ -218,7 +281,7 @@ int orc_lattice_create(const orc_lattice_desc* d, orc_lattice** out) {
     *out = NULL;
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) { set_err("bad dims"); return ORC_EINVAL; }
     if (!(d->tau > 0.5)) { set_err("tau must exceed 1/2"); return ORC_EINVAL; }
-    int zh_axis = -1;
+    int zh_axis = -1, zh_axes = 0;
     for (int a = 0; a < 3; ++a) {
         int lo = d->bc[2 * a], hi = d->bc[2 * a + 1];
         if (lo < 0 || lo > 2 || hi < 0 || hi > 2) { set_err("bad bc"); return ORC_EINVAL; }
@@ -226,17 +289,30 @@ int orc_lattice_create(const orc_lattice_desc* d, orc_lattice** out) {
             set_err("a periodic face needs a periodic partner"); return ORC_EINVAL;
         }
         if (lo == ORC_BC_ZOUHE || hi == ORC_BC_ZOUHE) {
-            if (zh_axis >= 0) { set_err("Zou-He walls on one axis only"); return ORC_EINVAL; }
             zh_axis = a;
+            ++zh_axes;
             int n = a == 0 ? d->nx : (a == 1 ? d->ny : d->nz);
             if (n < 3) { set_err("Zou-He axis needs 3 nodes"); return ORC_EINVAL; }
         }
     }
-    if (zh_axis >= 0)
+    /* Zou-He walls on one axis: the other axes are periodic (channel).  On several axes (duct,
+     * closed box): every wall is Zou-He and moves only tangentially, so that the velocity of a
+     * node shared by two faces is well defined (edge and corner closure). */
+    if (zh_axes == 1)
         for (int a = 0; a < 3; ++a)
             if (a != zh_axis && d->bc[2 * a] != ORC_BC_PERIODIC) {
-                set_err("Zou-He walls need periodic tangential axes"); return ORC_EINVAL;
+                set_err("Zou-He walls on one axis need periodic tangential axes"); return ORC_EINVAL;
             }
+    if (zh_axes > 1)
+        for (int f = 0; f < 6; ++f) {
+            if (d->bc[f] == ORC_BC_PERIODIC) continue;
+            if (d->bc[f] != ORC_BC_ZOUHE) {
+                set_err("Zou-He walls on several axes: every wall must be Zou-He"); return ORC_EINVAL;
+            }
+            if (d->wall_u[f][f / 2] != 0.0) {
+                set_err("Zou-He walls on several axes: wall velocities must be tangential"); return ORC_EINVAL;
+            }
+        }
     int moving = 0;
     for (int a = 0; a < 3; ++a)
         for (int s = 0; s < 2; ++s)
@@ -250,6 +326,7 @@ int orc_lattice_create(const orc_lattice_desc* d, orc_lattice** out) {
     L->nx = d->nx; L->ny = d->ny; L->nz = d->nz;
     L->N = (long)d->nx * d->ny * d->nz;
     L->tau = d->tau;
+    L->zh_axes = zh_axes;
     memcpy(L->bc, d->bc, sizeof L->bc);
     memcpy(L->wall_u, d->wall_u, sizeof L->wall_u);
     memcpy(L->G, d->body_force, sizeof L->G);
@@ -298,8 +375,61 @@ static void moments(orc_lattice* L) {
     }
 }
 
-/* Apply the Zou-He closure (Sec. 1.1) to every node on a Zou-He face (the state must satisfy
- * the wall condition at every time level). */
+/* Zou-He faces a node lies on: side[a] = -1 (low face of axis a), +1 (high face) or 0.
+ * Returns how many. */
+static int zh_sides(const orc_lattice* L, int x, int y, int z, int32_t side[3]) {
+    const int c[3] = {x, y, z};
+    int nw = 0;
+    for (int a = 0; a < 3; ++a) {
+        side[a] = 0;
+        if (c[a] == 0 && L->bc[2 * a] == ORC_BC_ZOUHE) side[a] = -1;
+        else if (c[a] == dim(L, a) - 1 && L->bc[2 * a + 1] == ORC_BC_ZOUHE) side[a] = 1;
+        if (side[a]) ++nw;
+    }
+    return nw;
+}
+
+/* Closure of every edge and corner node of a box with Zou-He walls on several axes (reading of
+ * Sec. 1.1, see orc_corner_closure).  The node's wall velocity: zero along each of its wall
+ * normals, the mean of its faces' velocities along the other axes.  Its density conserves mass
+ * at the node: the populations coming in through its walls carry together what it sent out
+ * through them, rho = sum of the known f_i + sum over unknown i of the outgoing population
+ * opposite to i (after streaming: the node's own post-collision fs_opp(i); when a state is
+ * set: the unknown values as given, so the given density is kept). */
+static void close_edges(orc_lattice* L, int after_stream) {
+    if (L->zh_axes < 2) return;
+    const long N = L->N;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (int z = 0; z < L->nz; ++z)
+        for (int y = 0; y < L->ny; ++y)
+            for (int x = 0; x < L->nx; ++x) {
+                int32_t side[3];
+                const int nw = zh_sides(L, x, y, z, side);
+                if (nw < 2) continue;
+                double uw[3];
+                for (int d = 0; d < 3; ++d) {
+                    uw[d] = 0.0;
+                    if (side[d] != 0) continue;
+                    for (int a = 0; a < 3; ++a)
+                        if (side[a] != 0) uw[d] += L->wall_u[2 * a + (side[a] > 0)][d];
+                    uw[d] /= nw;
+                }
+                const long k = node(L, x, y, z);
+                double fl[Q], rho = 0.0;
+                for (int i = 0; i < Q; ++i) {
+                    fl[i] = L->f[i * N + k];
+                    int in = 0;
+                    for (int a = 0; a < 3; ++a)
+                        if (side[a] != 0 && E[i][a] == -side[a]) in = 1;
+                    rho += !in ? fl[i] : (after_stream ? L->fs[opposite(i) * N + k] : fl[i]);
+                }
+                orc_corner_closure(side, rho, uw, L->G, fl);
+                for (int i = 0; i < Q; ++i) L->f[i * N + k] = fl[i];
+            }
+}
+
+/* Apply the Zou-He closure (Sec. 1.1) to every node on a Zou-He face, then to the edges and
+ * corners (the state must satisfy the wall condition at every time level). */
 static void close_walls(orc_lattice* L) {
     const long N = L->N;
     for (int a = 0; a < 3; ++a)
@@ -313,6 +443,8 @@ static void close_walls(orc_lattice* L) {
                 for (int q1 = 0; q1 < n[b1]; ++q1) {
                     int p[3];
                     p[a] = c; p[b1] = q1; p[b2] = q2;
+                    int32_t side[3];
+                    if (zh_sides(L, p[0], p[1], p[2], side) > 1) continue;   /* edge or corner */
                     long k = node(L, p[0], p[1], p[2]);
                     double fl[Q];
                     for (int i = 0; i < Q; ++i) fl[i] = L->f[i * N + k];
@@ -320,6 +452,7 @@ static void close_walls(orc_lattice* L) {
                     for (int i = 0; i < Q; ++i) L->f[i * N + k] = fl[i];
                 }
         }
+    close_edges(L, 0);
 }
 
 int orc_lattice_init(orc_lattice* L, const double* rho, const double* u) {
@@ -372,9 +505,10 @@ static void collide_all(orc_lattice* L, int with_collision) {
     }
 }
 
-/* Streaming part of Eq. (evoleq), fs -> f: f_i(x) = fs_i(x - e_i) with periodic wrap; a source behind a bounce-back
- * wall returns the node's own opposite population plus the moving-wall term; a source behind a
- * Zou-He face is reconstructed by the closure afterwards. */
+/* Streaming part of Eq. (evoleq), fs -> f: f_i(x) = fs_i(x - e_i) with periodic wrap; a source
+ * behind a bounce-back wall returns the node's own opposite population plus the moving-wall
+ * term; a source behind a Zou-He face is reconstructed by the face closure, or on edges and
+ * corners by the edge closure once every node has streamed. */
 static void stream_all(orc_lattice* L) {
     const long N = L->N;
     const int n[3] = {L->nx, L->ny, L->nz};
@@ -418,10 +552,12 @@ static void stream_all(orc_lattice* L) {
                         zh_face = out_face[0];
                     }
                 }
-                if (zh_face >= 0)
+                int32_t side[3];
+                if (zh_face >= 0 && zh_sides(L, x, y, z, side) == 1)
                     orc_wall_closure(zh_face / 2, (zh_face % 2) ? 1 : -1, L->wall_u[zh_face], L->G, fl);
                 for (int i = 0; i < Q; ++i) L->f[i * N + k] = fl[i];
             }
+    close_edges(L, 1);
 }
 
 int orc_stream_only(orc_lattice* L, int nsteps) {

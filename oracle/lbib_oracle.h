@@ -57,6 +57,10 @@ void orc_guo_forcing(double tau, const double u[3], const double F[3], double Fi
 void orc_collide_node(double tau, const double f[19], const double F[3], double fout[19]);
 /* Zou-He closure on a face node: axis 0..2, side -1 (low face) or +1 (high face). */
 void orc_wall_closure(int axis, int side, const double uw[3], const double F[3], double f[19]);
+/* Closure on a node on two or three Zou-He faces: side[a] = -1, +1 or 0 per axis, rho the
+ * node's density (taken from the node diagonally inside).  0, or -1 if singular. */
+int orc_corner_closure(const int32_t side[3], double rho, const double uw[3], const double F[3],
+                       double f[19]);
 
 /* --- lattice --- */
 int  orc_lattice_create(const orc_lattice_desc* d, orc_lattice** out);

@@ -164,6 +164,45 @@ def closed_box() -> dict:
     return dict(bc=(BC_BOUNCEBACK,) * 6, wall_u=((0.0, 0.0, 0.0),) * 6)
 
 
+def lid_cavity(u_lid: float) -> dict:
+    """Closed box of Zou-He velocity walls: the high-y wall (the lid) slides along +z at u_lid,
+    the other five rest (the lid-driven cavity of Sec. 2.1)."""
+    wall_u = [(0.0, 0.0, 0.0)] * 6
+    wall_u[3] = (0.0, 0.0, float(u_lid))
+    return dict(bc=(BC_ZOUHE_VELOCITY,) * 6, wall_u=tuple(wall_u))
+
+
+def cavity_spec(n: int, reynolds: float, tau: float = 1.0, storage: int = STORE_F32) -> LatticeSpec:
+    """Lid-driven cube of n nodes per side, walls on the first and last nodes (side L = n - 1):
+    lid speed from Re = u L / nu with nu = (tau - 1/2) / 3 (Sec. 2.1 keeps tau = 1)."""
+    nu = (tau - 0.5) / 3.0
+    u = reynolds * nu / (n - 1)
+    return LatticeSpec(n, n, n, tau, storage=storage, **lid_cavity(u))
+
+
+def square_duct(u_wall: float = 0.0) -> dict:
+    """Zou-He walls on the y and z faces, periodic along x; every wall slides along x at u_wall."""
+    return dict(bc=(BC_PERIODIC, BC_PERIODIC) + (BC_ZOUHE_VELOCITY,) * 4,
+                wall_u=((0.0, 0.0, 0.0),) * 2 + ((float(u_wall), 0.0, 0.0),) * 4)
+
+
+def duct_poiseuille(y, z, width: float, accel: float, nu: float, terms: int = 200) -> np.ndarray:
+    """Fully developed flow along x in a square duct of side `width` (walls at 0 and width in y
+    and z) driven by a uniform acceleration: the Fourier-series solution of
+    nu (u_yy + u_zz) = -accel with u = 0 on the walls."""
+    a = 0.5 * width
+    yc = np.asarray(y, dtype=np.float64) - a
+    zc = np.asarray(z, dtype=np.float64) - a
+    u = np.zeros(np.broadcast(yc, zc).shape)
+    for j in range(terms):
+        n = 2 * j + 1
+        k = n * np.pi / (2.0 * a)
+        # cosh(k z) / cosh(k a), written with exponentials that cannot overflow
+        ratio = (np.exp(k * (np.abs(zc) - a)) + np.exp(-k * (np.abs(zc) + a))) / (1.0 + np.exp(-2.0 * k * a))
+        u += (-1.0) ** j / n ** 3 * (1.0 - ratio) * np.cos(k * yc)
+    return 16.0 * a * a * accel / (nu * np.pi ** 3) * u
+
+
 def ks0_from_capillary(ca: float, tau: float, shear_rate: float, radius: float,
                        rho: float = 1.0) -> float:
     """Global spring constant from the capillary number Ca = rho*nu*u_ref/k_s0 (Sec. 1.3,
