@@ -47,7 +47,8 @@ typedef enum {
     LBIB_EINVAL = -1,    /* bad argument, descriptor or mesh */
     LBIB_ENOMEM = -2,    /* device allocation, workspace or memory budget exceeded */
     LBIB_EDEVICE = -3,   /* HIP runtime error; message from hipGetErrorString */
-    LBIB_EUNSTABLE = -4, /* non-finite density, position or rigid state detected */
+    LBIB_EUNSTABLE = -4, /* non-finite density, position or rigid state, or a density outside
+                            (0.05, 8) after streaming, detected */
     LBIB_EBUSY = -5,     /* server has no free slot / job still running */
     LBIB_ENOENT = -6,    /* no such body, job or result */
     LBIB_EDOMAIN = -7    /* an MLS support or probe left the fluid domain, or a body outgrew
@@ -55,9 +56,15 @@ typedef enum {
 } lbib_status;
 
 /* Face boundary kinds.  Faces are ordered -x,+x,-y,+y,-z,+z.  Both faces of an axis are
- * periodic or both are walls.  Zou-He walls sit on the first/last node of their axis (wet
- * nodes) and need the two other axes periodic; halfway bounce-back walls sit half a spacing
- * outside the first/last node; moving bounce-back walls on one axis only. */
+ * periodic or both are walls.  Zou-He walls (Sec. 1.1) sit on the first/last node of their
+ * axis (wet nodes), which needs at least 3 nodes.  On one axis they form a channel: the two
+ * other axes periodic, any wall velocity.  On two or three axes (a square duct, the closed
+ * lid-driven cavity of Sec. 2.1) every wall must be Zou-He and move tangentially; edge and
+ * corner nodes then take the wall velocity zero along their wall normals and the mean of their
+ * faces' velocities along the other axes, and a closure that keeps their mass balanced through
+ * the walls and sets their momentum to rho u_w - F/2 (the paper leaves edges and corners open).
+ * Halfway bounce-back walls sit half a spacing outside the first/last node; moving bounce-back
+ * walls on one axis only.  Other combinations fail with LBIB_EINVAL. */
 typedef enum { LBIB_BC_PERIODIC = 0, LBIB_BC_ZOUHE_VELOCITY = 1, LBIB_BC_BOUNCEBACK = 2 } lbib_bc;
 
 /* Population storage.  All forms store the deviation g_i = f_i - w_i from the lattice

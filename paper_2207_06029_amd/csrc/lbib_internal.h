@@ -76,7 +76,7 @@ struct JobDev {
     float omega;          // 1 / tau
     float guo;            // 1 - 1/(2 tau)
     float nu;             // (tau - 1/2) / 3
-    int zh_axis;          // axis carrying Zou-He walls, -1 if none
+    int zh_axes;          // axes carrying Zou-He walls (more than one: edge and corner closure)
     int bc[6];
     float wall_u[6][3];
     float G[3];           // uniform body force density

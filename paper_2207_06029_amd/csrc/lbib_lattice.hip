@@ -83,13 +83,144 @@ __device__ __forceinline__ void zou_he(const JobDev& J, int a, int side, float g
     }
 }
 
+// Inverse of the weighted moment matrix sum over unknown i of w_i (1, e_i)(1, e_i)^T of the
+// populations an edge or corner node receives through its walls, for every wall configuration
+// (index (s0 + 1) + 3 (s1 + 1) + 9 (s2 + 1), s_a as below), evaluated at compile time; zero
+// where the node lies on fewer than two walls.  The matrix depends only on the configuration,
+// so the kernel keeps no accumulators for it.
+struct CornerInv { float a[4][4]; };
+struct CornerTable { CornerInv t[27]; };
+constexpr CornerTable make_corner_table() {
+    CornerTable T{};
+    for (int t = 0; t < 27; ++t) {
+        const int s[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+        if ((s[0] != 0) + (s[1] != 0) + (s[2] != 0) < 2) continue;
+        double M[4][8] = {};   // [A | I], reduced to [I | A^-1]
+        for (int i = 0; i < Q; ++i) {
+            bool unk = false;
+            for (int a = 0; a < 3; ++a)
+                if (s[a] != 0 && ce(i, a) == -s[a]) unk = true;
+            if (!unk) continue;
+            const double p[4] = {1.0, (double)cx(i), (double)cy(i), (double)cz(i)};
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) M[r][c] += wq(i) * p[r] * p[c];
+        }
+        for (int r = 0; r < 4; ++r) M[r][4 + r] = 1.0;
+        for (int c = 0; c < 4; ++c) {   // Gauss-Jordan; A is symmetric positive definite
+            const double piv = M[c][c];
+            for (int k = 0; k < 8; ++k) M[c][k] /= piv;
+            for (int r = 0; r < 4; ++r) {
+                if (r == c) continue;
+                const double f = M[r][c];
+                for (int k = 0; k < 8; ++k) M[r][k] -= f * M[c][k];
+            }
+        }
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) T.t[t].a[r][c] = (float)M[r][4 + c];
+    }
+    return T;
+}
+// every entry inverts its matrix (checked when compiling)
+constexpr bool corner_table_ok() {
+    const CornerTable T = make_corner_table();
+    for (int t = 0; t < 27; ++t) {
+        const int s[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+        if ((s[0] != 0) + (s[1] != 0) + (s[2] != 0) < 2) continue;
+        double M[4][4] = {};
+        for (int i = 0; i < Q; ++i) {
+            bool unk = false;
+            for (int a = 0; a < 3; ++a)
+                if (s[a] != 0 && ce(i, a) == -s[a]) unk = true;
+            if (!unk) continue;
+            const double p[4] = {1.0, (double)cx(i), (double)cy(i), (double)cz(i)};
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) M[r][c] += wq(i) * p[r] * p[c];
+        }
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 4; ++k) acc += M[r][k] * (double)T.t[t].a[k][c];
+                const double err = acc - (r == c ? 1.0 : 0.0);
+                if (err > 1e-5 || err < -1e-5) return false;
+            }
+    }
+    return true;
+}
+static_assert(corner_table_ok(), "edge and corner moment inverses inconsistent");
+__constant__ const CornerTable kCornerInv = make_corner_table();
+
+// Edge or corner node of a box with Zou-He walls on several axes (s_a = -1 / +1 on the low /
+// high wall of axis a, 0 off the walls of a).  The paper leaves these nodes open; they are
+// closed as follows.  Unknown are the populations streamed in through any of the node's walls.
+// On entry their slots hold the redirected loads, the node's own outgoing deviations opposite to
+// them, so the sum of g balances the node's mass through its walls and gives its density.  The
+// wall velocity is zero along the node's wall normals and the mean of its faces' velocities
+// along the other axes.  An unknown whose opposite is known takes it plus 6 w_i (e_i . m)
+// (bounce-back of the non-equilibrium part); one whose opposite is unknown too (a link buried
+// in the wall) takes the equilibrium.  A correction w_i (l0 + l . e_i) over the unknowns, l the
+// inverse of their weighted moment matrix applied to the residual, then sets the mass and the
+// momentum m = rho u_w - G/2 exactly.
+__device__ __forceinline__ void zou_he_corner(const JobDev& J, int s0, int s1, int s2, float g[Q]) {
+    float drho = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) drho += g[i];
+    const float rho = 1.f + drho;
+    const float inw = 1.f / (float)((s0 != 0) + (s1 != 0) + (s2 != 0));
+    float uw[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        float acc = 0.f;
+        if (s0) acc += J.wall_u[s0 > 0 ? 1 : 0][d];
+        if (s1) acc += J.wall_u[s1 > 0 ? 3 : 2][d];
+        if (s2) acc += J.wall_u[s2 > 0 ? 5 : 4][d];
+        const int sd = d == 0 ? s0 : (d == 1 ? s1 : s2);
+        uw[d] = sd != 0 ? 0.f : acc * inw;
+    }
+    const float m0 = rho * uw[0] - 0.5f * J.G[0];
+    const float m1 = rho * uw[1] - 0.5f * J.G[1];
+    const float m2 = rho * uw[2] - 0.5f * J.G[2];
+    const float uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+    // unknown: e_i points into the fluid through one of the node's walls
+#define LBIB_UNK(i) ((s0 != 0 && cx(i) == -s0) || (s1 != 0 && cy(i) == -s1) || (s2 != 0 && cz(i) == -s2))
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (!LBIB_UNK(i)) continue;
+        const float w = (float)wq(i);
+        if (!LBIB_UNK(opp(i))) {
+            g[i] = g[opp(i)] + 6.f * w * (cx(i) * m0 + cy(i) * m1 + cz(i) * m2);
+        } else {
+            const float eu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
+            g[i] = w * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
+        }
+    }
+    // residual of mass and momentum
+    float r0 = drho, r1 = m0, r2 = m1, r3 = m2;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        r0 -= g[i];
+        if (cx(i)) r1 -= cx(i) * g[i];
+        if (cy(i)) r2 -= cy(i) * g[i];
+        if (cz(i)) r3 -= cz(i) * g[i];
+    }
+    const CornerInv& A = kCornerInv.t[(s0 + 1) + 3 * (s1 + 1) + 9 * (s2 + 1)];
+    const float x0 = A.a[0][0] * r0 + A.a[0][1] * r1 + A.a[0][2] * r2 + A.a[0][3] * r3;
+    const float x1 = A.a[1][0] * r0 + A.a[1][1] * r1 + A.a[1][2] * r2 + A.a[1][3] * r3;
+    const float x2 = A.a[2][0] * r0 + A.a[2][1] * r1 + A.a[2][2] * r2 + A.a[2][3] * r3;
+    const float x3 = A.a[3][0] * r0 + A.a[3][1] * r1 + A.a[3][2] * r2 + A.a[3][3] * r3;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        if (LBIB_UNK(i)) g[i] += (float)wq(i) * (x0 + cx(i) * x1 + cy(i) * x2 + cz(i) * x3);
+#undef LBIB_UNK
+}
+
 // ---------------------------------------------------------------- pull
 // Post-streaming deviations at node (x, y, z) of job J from the post-collision buffer src.
 // All 19 loads are issued unconditionally, so they are in flight together: a source outside
 // the domain is redirected to the node's own opposite population (the halfway bounce-back
 // source, always a valid address), and the wall term or the Zou-He closure is applied once
-// the loads have returned.
-template <typename S>
+// the loads have returned.  Without ZH_CLOSURE the populations of Zou-He wall nodes stay
+// unclosed (finite but meaningless): for readers that never look at those nodes.
+template <typename S, bool ZH_CLOSURE = true>
 __device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J, int x, int y,
                                      int z, long long k, float g[Q]) {
     const long long N = J.n;
@@ -139,14 +270,19 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J,
             const float eu = e0 * uwx + e1 * uwy + e2 * uwz;
             g[i] = g[i] + (float)(6.0 * wq(i)) * eu;
         } else {
-            g[i] = 0.f;
-            unknown = true;
+            unknown = true;   // rebuilt by the closure; the slot keeps the redirected load
         }
     }
-    if (unknown) {
-        const int a = J.zh_axis;
-        const int c = a == 0 ? x : (a == 1 ? y : z);
-        zou_he(J, a, c == 0 ? 0 : 1, g);
+    if (ZH_CLOSURE && unknown) {
+        const int s0 = oxm && J.bc[0] == 1 ? -1 : (oxp && J.bc[1] == 1 ? 1 : 0);
+        const int s1 = oym && J.bc[2] == 1 ? -1 : (oyp && J.bc[3] == 1 ? 1 : 0);
+        const int s2 = ozm && J.bc[4] == 1 ? -1 : (ozp && J.bc[5] == 1 ? 1 : 0);
+        if ((s0 != 0) + (s1 != 0) + (s2 != 0) == 1) {
+            const int a = s0 ? 0 : (s1 ? 1 : 2);
+            zou_he(J, a, (s0 + s1 + s2) > 0 ? 1 : 0, g);
+        } else {
+            zou_he_corner(J, s0, s1, s2, g);
+        }
     }
 }
 
@@ -215,7 +351,9 @@ __device__ __forceinline__ void sweep_node(const Pools& P, const JobDev& J, cons
         const float uu = ux * ux + uy * uy + uz * uz;
         const float uF = ux * F[0] + uy * F[1] + uz * F[2];
         const float om = J.omega, gk = J.guo;
-        if (!(fabsf(drho) < 0.5f)) atomicOr(P.flags + job, FLAG_NONFINITE);
+        // runaway sentinel: non-finite, or a density no flow of the scheme reaches (the singular
+        // lid edges of a cavity at lid Mach 0.6 reach about 2.7)
+        if (!(drho > -0.95f && drho < 7.f)) atomicOr(P.flags + job, FLAG_NONFINITE);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const float w = (float)wq(i);
@@ -308,8 +446,10 @@ __global__ void __launch_bounds__(256) k_window_moments(Pools P, int from_b) {
         if (y >= J.ny) y -= J.ny;
         if (z >= J.nz) z -= J.nz;
         const long long k = x + (long long)J.nx * (y + (long long)J.ny * z);
+        // MLS supports exclude Zou-He wall nodes (their moments are never read), so the pull
+        // skips the Zou-He closure here
         float g[Q];
-        pull<S>(src, J, x, y, z, k, g);
+        pull<S, false>(src, J, x, y, z, k, g);
         float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -373,7 +513,9 @@ __global__ void k_get_pops(Pools P, int from_b, int job, float* out) {
 }
 
 // Inverse of the pull: write the post-collision entries whose pull reproduces f.  Entries
-// pulled from behind a Zou-He face are not representable; the closure rebuilds them.
+// pulled from behind a Zou-He face are not representable; the closure rebuilds them, on edges
+// and corners from a density that the given unknown values, stored in the redirected slots,
+// make equal to the given one.
 template <typename S>
 __global__ void k_set_pops(Pools P, int to_b, int job, const double* f) {
     const JobDev& J = P.jobs[job];
@@ -410,6 +552,10 @@ __global__ void k_set_pops(Pools P, int to_b, int job, const double* f) {
         } else if (!zh && J.bc[face] == 2) {
             const float eu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
             Codec<S>::st(dst + (long long)opp(i) * J.n + k, gi - (float)(6.0 * wq(i)) * eu);
+        } else if (zh) {
+            // the redirected slot: the edge and corner closure reads it as the mass the node
+            // sent out through its walls, so the given density is kept
+            Codec<S>::st(dst + (long long)opp(i) * J.n + k, gi);
         }
     }
 }

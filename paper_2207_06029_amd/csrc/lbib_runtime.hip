@@ -88,15 +88,15 @@ lbib_status check_lattice(const lbib_lattice_desc& d) {
     if ((long long)d.nx * d.ny * d.nz >= (1LL << 31)) return fail(LBIB_EINVAL, "lattice too large");
     if (!(d.tau > 0.5)) return fail(LBIB_EINVAL, "tau must exceed 1/2");
     if (d.storage < 0 || d.storage > 2) return fail(LBIB_EINVAL, "unknown storage");
-    int zh = -1, moving = 0;
+    int zh = -1, nzh = 0, moving = 0;
     const int n[3] = {d.nx, d.ny, d.nz};
     for (int a = 0; a < 3; ++a) {
         const int lo = d.bc[2 * a], hi = d.bc[2 * a + 1];
         if (lo < 0 || lo > 2 || hi < 0 || hi > 2) return fail(LBIB_EINVAL, "unknown boundary kind");
         if ((lo == 0) != (hi == 0)) return fail(LBIB_EINVAL, "a periodic face needs a periodic partner");
         if (lo == 1 || hi == 1) {
-            if (zh >= 0) return fail(LBIB_EINVAL, "Zou-He walls on one axis only");
             zh = a;
+            ++nzh;
             if (n[a] < 3) return fail(LBIB_EINVAL, "a Zou-He axis needs at least 3 nodes");
         }
         for (int s = 0; s < 2; ++s)
@@ -104,9 +104,20 @@ lbib_status check_lattice(const lbib_lattice_desc& d) {
                                          d.wall_u[2 * a + s][2] != 0))
                 moving |= 1 << a;
     }
-    if (zh >= 0)
+    // Zou-He walls on one axis: a channel between periodic axes.  On several axes (duct, closed
+    // box) their edges and corners are closed too, which needs every wall to be Zou-He and to
+    // move tangentially (one velocity per edge node).
+    if (nzh == 1)
         for (int a = 0; a < 3; ++a)
-            if (a != zh && d.bc[2 * a] != 0) return fail(LBIB_EINVAL, "Zou-He walls need periodic tangential axes");
+            if (a != zh && d.bc[2 * a] != 0)
+                return fail(LBIB_EINVAL, "Zou-He walls on one axis need periodic tangential axes");
+    if (nzh > 1)
+        for (int f = 0; f < 6; ++f) {
+            if (d.bc[f] == 0) continue;
+            if (d.bc[f] != 1) return fail(LBIB_EINVAL, "Zou-He walls on several axes: every wall must be Zou-He");
+            if (d.wall_u[f][f / 2] != 0)
+                return fail(LBIB_EINVAL, "Zou-He walls on several axes: wall velocities must be tangential");
+        }
     if (moving & (moving - 1)) return fail(LBIB_EINVAL, "moving bounce-back walls on one axis only");
     return LBIB_OK;
 }
@@ -342,12 +353,12 @@ void Batch::job_from_desc(const lbib_lattice_desc& d, JobDev& J) {
     J.omega = (float)(1.0 / d.tau);
     J.guo = (float)(1.0 - 1.0 / (2.0 * d.tau));
     J.nu = (float)((d.tau - 0.5) / 3.0);
-    J.zh_axis = -1;
     for (int f = 0; f < 6; ++f) {
         J.bc[f] = d.bc[f];
-        if (d.bc[f] == 1) J.zh_axis = f / 2;
         for (int a = 0; a < 3; ++a) J.wall_u[f][a] = (float)d.wall_u[f][a];
     }
+    for (int a = 0; a < 3; ++a)
+        if (d.bc[2 * a] == 1 || d.bc[2 * a + 1] == 1) ++J.zh_axes;
     for (int a = 0; a < 3; ++a) J.G[a] = (float)d.body_force[a];
 }
 

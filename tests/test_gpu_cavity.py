@@ -1,0 +1,140 @@
+"""Zou-He walls on several axes on the GPU: the edge and corner closure against the FP64 oracle
+(streaming, set/get, forced duct, lid-driven cavity in FP32 and FP16), the square-duct flow
+against its Fourier series, and the second-order self-convergence of the lid-driven cavity at
+the paper's Re = 100, tau = 1 (Sec. 2.1)."""
+import numpy as np
+import pytest
+
+from paper_2207_06029_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2207_06029_amd import api as A
+    return A
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_streaming_closed_zouhe_box_matches_oracle(api, orc):
+    """Pure streaming of random populations through a closed box of resting Zou-He walls: face,
+    edge and corner closures rebuild the unknowns from the redirected loads."""
+    spec = I.LatticeSpec(9, 7, 11, 0.8, bc=(I.BC_ZOUHE_VELOCITY,) * 6)
+    lat = api.Lattice(spec)
+    ref = orc.Lattice(spec)
+    f = I.random_populations(spec.n, seed=21)
+    lat.set_populations(f)
+    ref.set_populations(f)
+    np.testing.assert_allclose(lat.populations(), ref.populations(), rtol=0, atol=2e-7)
+    lat.stream_only(3)
+    ref.stream_only(3)
+    np.testing.assert_allclose(lat.populations(), ref.populations(), rtol=0, atol=6e-7)
+
+
+@pytest.mark.parametrize("storage,tol", [(I.STORE_F32, 3e-6), (I.STORE_F16, 1e-3)])
+def test_lid_cavity_matches_oracle(api, orc, storage, tol):
+    spec = I.LatticeSpec(13, 13, 13, 0.8, storage=storage, **I.lid_cavity(0.05))
+    lat = api.Lattice(spec)
+    ref = orc.Lattice(spec)
+    lat.step(300)
+    ref.step(300)
+    rho, u = lat.macros()
+    rr, ur = ref.macros()
+    err = rel_l2(u, ur)
+    print(f"cavity 13^3, storage {storage}: rel-L2 u* {err:.3e}, max |drho| {np.abs(rho - rr).max():.2e}")
+    assert err < tol
+    if storage == I.STORE_F32:
+        assert np.abs(rho - rr).max() < 2e-7
+
+
+def test_forced_sliding_duct_matches_oracle(api, orc):
+    """Ragged duct (x periodic) with walls sliding along x and a body force across it."""
+    spec = I.LatticeSpec(5, 11, 13, 0.7, body_force=(2e-6, 1e-6, -5e-7), **I.square_duct(0.02))
+    lat = api.Lattice(spec)
+    ref = orc.Lattice(spec)
+    rho0, u0 = I.random_fields((5, 11, 13), seed=8, amp_u=1e-2)
+    lat.init(rho0, u0)
+    ref.init(rho0, u0)
+    lat.step(200)
+    ref.step(200)
+    rho, u = lat.macros()
+    rr, ur = ref.macros()
+    assert rel_l2(u, ur) < 3e-6
+    assert np.abs(rho - rr).max() < 2e-7
+
+
+def test_square_duct_poiseuille_closed_form(api):
+    n, tau = 33, 1.0
+    nu = (tau - 0.5) / 3.0
+    width = n - 1
+    accel = 0.02 * 32.0 * nu / width ** 2
+    spec = I.LatticeSpec(4, n, n, tau, body_force=(accel, 0.0, 0.0), **I.square_duct())
+    lat = api.Lattice(spec)
+    lat.step(8 * width * width + 200)
+    rho, u = lat.macros()
+    ug = (u[0] + accel / (2.0 * rho)).reshape(n, n, 4)[:, :, 1]
+    exact = I.duct_poiseuille(np.arange(n)[None, :], np.arange(n)[:, None], width, accel, nu)
+    err = np.abs(ug - exact).max() / exact.max()
+    print(f"duct 32 spacings: max rel error {err:.3e} (FP64 oracle at this size: 7.7e-4)")
+    assert err < 1.0e-3
+
+
+def test_batch_mixing_cavity_and_shear_jobs_bitwise(api):
+    jobs = I.capsule_batch(seed=2, njobs=2, storage=I.STORE_F16, steps=50)
+    cav = I.cavity_spec(25, 10.0, tau=0.8, storage=I.STORE_F16)
+    jobs.append(I.Job("cavity", cav, None, None, None, 50, tag=5))
+    mix = api.Batch(jobs, storage=I.STORE_F16)
+    mix.step(50)
+    mix.sync()
+    for j, job in enumerate(jobs):
+        alone = api.Batch([job], storage=I.STORE_F16)
+        alone.step(50)
+        alone.sync()
+        np.testing.assert_array_equal(mix.lattice(j).macros()[1], alone.lattice(0).macros()[1])
+
+
+def _centrelines(api, n, steps, chunk):
+    spec = I.cavity_spec(n, 100.0, tau=1.0)
+    lat = api.Lattice(spec)
+    m = (n - 1) // 2
+    prev = None
+    change = None
+    done = 0
+    while done < steps:
+        lat.step(chunk)
+        done += chunk
+        _, u = lat.macros()
+        uz = u[2].reshape(n, n, n)[m, :, m]        # u_z along y at x = z = L/2
+        uy = u[1].reshape(n, n, n)[:, m, m]        # u_y along z at x = y = L/2
+        line = np.concatenate([uz, uy])
+        if prev is not None:
+            change = np.abs(line - prev).max()
+        prev = line
+    u_lid = spec.wall_u[3][2]
+    return uz / u_lid, uy / u_lid, change / u_lid
+
+
+def test_lid_cavity_second_order_self_convergence(api):
+    """Re = 100 with tau = 1 on cubes of L = 48, 96 and 192 spacings (lid speed 100 nu / L, so
+    that the Mach number falls with the spacing, as in the paper's refinement).  Profiles on the
+    two centrelines at the coarse grid's nodes; the differences between successive grids fall
+    by about four."""
+    lines = {}
+    for L in (48, 96, 192):
+        steps = int(2.5 * L * L)
+        chunk = max(500, steps // 20)
+        uz, uy, change = _centrelines(api, L + 1, steps, chunk)
+        stride = L // 48
+        lines[L] = np.concatenate([uz[::stride], uy[::stride]])
+        print(f"L={L}: {steps} steps, last-chunk change {change:.2e} of the lid speed, "
+              f"min u_z/u_lid {uz.min():.4f}")
+        assert change < 1e-5
+    d1 = np.linalg.norm(lines[48] - lines[96]) / np.linalg.norm(lines[96])
+    d2 = np.linalg.norm(lines[96] - lines[192]) / np.linalg.norm(lines[192])
+    order = np.log2(d1 / d2)
+    print(f"centreline differences: 48-96 {d1:.3e}, 96-192 {d2:.3e}, observed order {order:.2f}")
+    assert 1.6 < order < 2.6

@@ -109,3 +109,18 @@ def test_batch_with_fluid_only_job_alone_vs_mix_bitwise(api):
         _, um = mix.lattice(j).macros()
         _, ua = alone.lattice(0).macros()
         np.testing.assert_array_equal(um, ua)
+
+
+@pytest.mark.parametrize("value", [float("nan"), 21.0])
+def test_runaway_state_reports_unstable(api, value):
+    """A node whose populations are non-finite, or whose density leaves (0.05, 8), raises
+    LBIB_EUNSTABLE at the next synchronisation (the condition is set from the host as data)."""
+    spec = I.LatticeSpec(8, 6, 5, 0.8)
+    lat = api.Lattice(spec)
+    f = I.random_populations(spec.n, seed=9)
+    f[:, 17] = value
+    lat.set_populations(f)
+    lat.step(1)
+    with pytest.raises(api.L.LbibError) as ei:
+        lat.sync()
+    assert ei.value.code == -4
