@@ -318,6 +318,85 @@ __device__ void hinge_forces(const Pools& P, const BodyDev& B, int e, double out
     }
 }
 
+// ---------------------------------------------------------------- spreading
+// The 16 markers of a block are neighbours on the mesh, so their stencils overlap: about 9
+// active nodes per marker, but only about 1.7 distinct nodes per marker over the block.  The
+// block therefore sums its contributions in LDS first (int64, so the order cannot change the
+// sum) and sends one global atomic per distinct node and component.  The LDS box is the
+// bounding box of the block's 3x3x3 stencils in unwrapped node coordinates; a block whose box
+// exceeds SPREAD_LDS_NODES (markers far apart on the lattice) adds straight to global memory.
+constexpr int SPREAD_LDS_NODES = 512;
+
+__device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, const BodyDev& B,
+                                             const WinDesc& fd, bool live, const int cen_node[3],
+                                             int lane, const long long wl[MLS_NODES],
+                                             const long long fx[MLS_NODES][3]) {
+    __shared__ long long s_acc[3][SPREAD_LDS_NODES];
+    __shared__ int s_box[4][6];
+    const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+    unsigned long long* fw0 = (unsigned long long*)(P.fwin + 3 * B.win_off);
+    // block box: wave min/max of the live markers' stencil corners, then over the 4 waves
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = live ? cen_node[a] - 1 : 0x3fffffff;
+        hi[a] = live ? cen_node[a] + 1 : -0x3fffffff;
+    }
+    for (int o = 32; o >= 1; o >>= 1)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
+        }
+    const int wave = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) { s_box[wave][a] = lo[a]; s_box[wave][3 + a] = hi[a]; }
+    for (int i = threadIdx.x; i < 3 * SPREAD_LDS_NODES; i += blockDim.x) (&s_acc[0][0])[i] = 0;
+    __syncthreads();
+    int o[3], w[3];
+    long long vol = 1;
+    for (int a = 0; a < 3; ++a) {
+        int l = s_box[0][a], h = s_box[0][3 + a];
+        for (int q = 1; q < 4; ++q) { l = min(l, s_box[q][a]); h = max(h, s_box[q][3 + a]); }
+        o[a] = l;
+        w[a] = h >= l ? h - l + 1 : 1;
+        vol *= w[a];
+    }
+    const bool use_lds = vol <= SPREAD_LDS_NODES;   // uniform over the block
+#pragma unroll
+    for (int sn = 0; sn < MLS_NODES; ++sn) {
+        if (wl[sn] < 0) continue;
+        if (use_lds) {
+            const int k = lane + GROUP * sn;
+            const int li = (cen_node[0] + k % 3 - 1 - o[0]) +
+                           w[0] * ((cen_node[1] + (k / 3) % 3 - 1 - o[1]) + w[1] * (cen_node[2] + k / 9 - 1 - o[2]));
+            for (int c = 0; c < 3; ++c)
+                if (fx[sn][c]) atomicAdd((unsigned long long*)&s_acc[c][li], (unsigned long long)fx[sn][c]);
+        } else {
+            for (int c = 0; c < 3; ++c)
+                if (fx[sn][c]) atomicAdd(fw0 + c * capn + wl[sn], (unsigned long long)fx[sn][c]);
+        }
+    }
+    if (!use_lds) return;
+    __syncthreads();
+    const int dims[3] = {J.nx, J.ny, J.nz};
+    for (int i = threadIdx.x; i < (int)vol; i += blockDim.x) {
+        const long long v0 = s_acc[0][i], v1 = s_acc[1][i], v2 = s_acc[2][i];
+        if (!(v0 | v1 | v2)) continue;
+        // back to wrapped lattice coordinates; only nodes with a window index received sums
+        // (a support node beyond a wall has already raised the domain error; it is dropped)
+        int g[3] = {o[0] + i % w[0], o[1] + (i / w[0]) % w[1], o[2] + i / (w[0] * w[1])};
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) {
+            if (J.bc[2 * a] == 0) { g[a] %= dims[a]; if (g[a] < 0) g[a] += dims[a]; }
+            else if (g[a] < 0 || g[a] >= dims[a]) inside = false;
+        }
+        const long long l = inside ? win_index(J, fd, g[0], g[1], g[2]) : -1;
+        if (l < 0) continue;
+        if (v0) atomicAdd(fw0 + l, (unsigned long long)v0);
+        if (v1) atomicAdd(fw0 + capn + l, (unsigned long long)v1);
+        if (v2) atomicAdd(fw0 + 2 * capn + l, (unsigned long long)v2);
+    }
+}
+
 // ---------------------------------------------------------------- centroids (+ hinges)
 __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fold) {
     if ((int)blockIdx.x >= nblk_tri) {
@@ -385,6 +464,9 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
         fd = P.fdesc[b];
     }
     double Vt = 0.0;
+    int cen_node[3] = {0, 0, 0};               // node nearest to the centroid (unwrapped)
+    long long wl[MLS_NODES] = {-1, -1};        // window index of each stencil node, -1 if none
+    long long fx[MLS_NODES][3];                // its fixed-point force contribution
     if (live) {
         double cen[3], ab[3], ac[3], N[3];
         for (int a = 0; a < 3; ++a) {
@@ -409,6 +491,7 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
         }
         MlsLane m;
         mls_setup(J, cen, B.rw2, lane, m, err);
+        for (int a = 0; a < 3; ++a) cen_node[a] = (int)floor(cen[a] + 0.5);
         float4 mom[MLS_NODES];
         mls_moments(P, J, B, b, m, mom, err);
         mls_solve(m, B.wq, false, err);
@@ -422,23 +505,23 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
             cross3(S.om, rr, w);
             for (int a = 0; a < 3; ++a) Ub[a] = S.u[a] + w[a];
         }
-        // F_l = (U_b - U*) / dt, spread with c_l = A_l h (Eq. bodyforce)
-        const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+        // F_l = (U_b - U*) / dt, spread with c_l = A_l h (Eq. bodyforce), as int64 fixed point
 #pragma unroll
         for (int sn = 0; sn < MLS_NODES; ++sn) {
+            fx[sn][0] = fx[sn][1] = fx[sn][2] = 0;
             if (!m.active[sn]) continue;
             const double sc = A * B.shell_h * m.phi[sn];
-            const long long l = win_index(J, fd, m.gx[sn], m.gy[sn], m.gz[sn]);
-            if (l < 0) {
+            wl[sn] = win_index(J, fd, m.gx[sn], m.gy[sn], m.gz[sn]);
+            if (wl[sn] < 0) {
                 err |= FLAG_WINDOW;
                 continue;
             }
-            unsigned long long* fw = (unsigned long long*)(P.fwin + 3 * B.win_off + l);
-            atomicAdd(fw, (unsigned long long)__double2ll_rn(sc * (Ub[0] - U0) * FIX_SCALE));
-            atomicAdd(fw + capn, (unsigned long long)__double2ll_rn(sc * (Ub[1] - U1) * FIX_SCALE));
-            atomicAdd(fw + 2 * capn, (unsigned long long)__double2ll_rn(sc * (Ub[2] - U2) * FIX_SCALE));
+            fx[sn][0] = __double2ll_rn(sc * (Ub[0] - U0) * FIX_SCALE);
+            fx[sn][1] = __double2ll_rn(sc * (Ub[1] - U1) * FIX_SCALE);
+            fx[sn][2] = __double2ll_rn(sc * (Ub[2] - U2) * FIX_SCALE);
         }
     }
+    spread_block(P, J, B, fd, live, cen_node, lane, wl, fx);
     if (err) atomicOr(P.flags + B.job, err);
     if (B.rigid || B.kv == 0.0) return;
     if (lane == 0) vol[grp] = Vt;
