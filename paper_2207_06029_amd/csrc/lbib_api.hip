@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <vector>
 #include <map>
 #include <memory>
 #include <sstream>
@@ -65,14 +66,28 @@ lbib_status autotune(Batch& B, const char* cache) {
     const std::string key = shape_key(B);
     std::map<std::string, SweepShape> table;
     if (cache) {
+        // one line per job mix: key, block, nodes per thread, XCD chunk (absent in older
+        // caches: chosen by footprint)
         std::ifstream in(cache);
-        std::string k;
-        int blk, npt;
-        while (in >> k >> blk >> npt) table[k] = SweepShape{blk, npt};
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            int blk, npt, chunk = -1;
+            if (!(ls >> k >> blk >> npt)) continue;
+            if (!(ls >> chunk)) chunk = -1;
+            table[k] = SweepShape{blk, npt, chunk};
+        }
         auto it = table.find(key);
         if (it != table.end()) return B.set_shape(it->second);
     }
-    const SweepShape cand[] = {{128, 1}, {256, 1}, {512, 1}, {1024, 1}, {256, 2}, {512, 2}, {256, 4}};
+    std::vector<SweepShape> cand;
+    for (const SweepShape& c : {SweepShape{128, 1, 0}, SweepShape{256, 1, 0}, SweepShape{512, 1, 0},
+                                SweepShape{1024, 1, 0}, SweepShape{256, 2, 0}, SweepShape{512, 2, 0},
+                                SweepShape{256, 4, 0}}) {
+        cand.push_back(c);
+        cand.push_back(SweepShape{c.block, c.npt, XCD_CHUNK});
+    }
     SweepShape best = B.shape;
     double best_ms = 1e30;
     struct Events {
@@ -89,11 +104,11 @@ lbib_status autotune(Batch& B, const char* cache) {
         if (st) return st;
         // sweeps from the current buffer into the other one; the state is not advanced
         for (int w = 0; w < 2; ++w)
-            launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tile_job.size(), c, B.stream);
+            launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tile_job.size(), c, B.xcd_chunk, B.stream);
         if (hipEventRecord(ev.e0, B.stream) != hipSuccess) return fail(LBIB_EDEVICE, "autotune event record failed");
         const int reps = 8;
         for (int r = 0; r < reps; ++r)
-            launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tile_job.size(), c, B.stream);
+            launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tile_job.size(), c, B.xcd_chunk, B.stream);
         if (hipEventRecord(ev.e1, B.stream) != hipSuccess) return fail(LBIB_EDEVICE, "autotune event record failed");
         if (hipEventSynchronize(ev.e1) != hipSuccess) return fail(LBIB_EDEVICE, "autotune sync failed");
         float ms = 0.f;
@@ -103,7 +118,8 @@ lbib_status autotune(Batch& B, const char* cache) {
     if (cache) {
         table[key] = best;
         std::ofstream out(cache);
-        for (auto& kv : table) out << kv.first << " " << kv.second.block << " " << kv.second.npt << "\n";
+        for (auto& kv : table)
+            out << kv.first << " " << kv.second.block << " " << kv.second.npt << " " << kv.second.xcd_chunk << "\n";
     }
     return B.set_shape(best);
 }

@@ -63,6 +63,13 @@ __device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], d
                                           MlsLane& m, int& err) {
     const int c0 = (int)floor(xp[0] + 0.5), c1 = (int)floor(xp[1] + 0.5), c2 = (int)floor(xp[2] + 0.5);
     const int dims[3] = {J.nx, J.ny, J.nz};
+    // the nearest node wrapped once per periodic axis; its neighbours then wrap by +-n
+    int cw[3] = {c0, c1, c2};
+    for (int a = 0; a < 3; ++a)
+        if (J.bc[2 * a] == 0) {
+            cw[a] %= dims[a];
+            if (cw[a] < 0) cw[a] += dims[a];
+        }
 #pragma unroll
     for (int s = 0; s < MLS_NODES; ++s) {
         const int k = lane + GROUP * s;
@@ -81,8 +88,9 @@ __device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], d
         for (int a = 0; a < 3; ++a) {
             const int bc = J.bc[2 * a];
             if (bc == 0) {
-                nn[a] %= dims[a];
+                nn[a] = cw[a] + (a == 0 ? k % 3 - 1 : (a == 1 ? (k / 3) % 3 - 1 : k / 9 - 1));
                 if (nn[a] < 0) nn[a] += dims[a];
+                else if (nn[a] >= dims[a]) nn[a] -= dims[a];
             } else {
                 const int lo = bc == 1 ? 1 : 0, hi = bc == 1 ? dims[a] - 2 : dims[a] - 1;
                 if (nn[a] < lo || nn[a] > hi) {
@@ -318,6 +326,18 @@ __device__ void hinge_forces(const Pools& P, const BodyDev& B, int e, double out
     }
 }
 
+// ---------------------------------------------------------------- fixed point
+// Round to nearest even into int64, as __double2ll_rn, without its software sequence: for
+// |v| < 2^51, v + 1.5 * 2^52 lies in [2^52, 2^53), where the addition itself rounds v to an
+// integer in the low mantissa bits.  The addition must not be fused with the product that
+// formed v.
+__device__ __forceinline__ long long fix_rn(double v) {
+#pragma clang fp contract(off)
+    if (!(fabs(v) < 2251799813685248.0)) return __double2ll_rn(v);
+    const double t = v + 6755399441055744.0;
+    return __double_as_longlong(t) - 0x4338000000000000LL;
+}
+
 // ---------------------------------------------------------------- spreading
 // The 16 markers of a block are neighbours on the mesh, so their stencils overlap: about 9
 // active nodes per marker, but only about 1.7 distinct nodes per marker over the block.  The
@@ -325,54 +345,90 @@ __device__ void hinge_forces(const Pools& P, const BodyDev& B, int e, double out
 // sum) and sends one global atomic per distinct node and component.  The LDS box is the
 // bounding box of the block's 3x3x3 stencils in unwrapped node coordinates; a block whose box
 // exceeds SPREAD_LDS_NODES (markers far apart on the lattice) adds straight to global memory.
+//
+// With fold set, the same block-wide reduction also folds the integer boxes that the vertex
+// blocks wrote for x^n into this step's force window (min / max, order independent): every
+// block derives the same descriptor and block 0 publishes it for the sweep and the moments.
+// vb[6] is this thread's vertex-block box (first entry; further ones are folded here).
+// Without fold, fd_in is the window the window kernel of the previous step published.
 constexpr int SPREAD_LDS_NODES = 512;
 
-__device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, const BodyDev& B,
-                                             const WinDesc& fd, bool live, const int cen_node[3],
-                                             int lane, const long long wl[MLS_NODES],
-                                             const long long fx[MLS_NODES][3]) {
+__device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, const BodyDev& B, int b,
+                                             int blk, bool fold, const int vb[6], const WinDesc& fd_in,
+                                             bool live, const int cen_node[3], const MlsLane& m,
+                                             int lane, const long long fx[MLS_NODES][3], int& err) {
     __shared__ long long s_acc[3][SPREAD_LDS_NODES];
-    __shared__ int s_box[4][6];
+    __shared__ int s_box[4][12];
     const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
     unsigned long long* fw0 = (unsigned long long*)(P.fwin + 3 * B.win_off);
-    // block box: wave min/max of the live markers' stencil corners, then over the 4 waves
-    int lo[3], hi[3];
+    // r[0..2] / r[3..5]: stencil box of the live markers; r[6..8] / r[9..11]: vertex boxes
+    int r[12];
     for (int a = 0; a < 3; ++a) {
-        lo[a] = live ? cen_node[a] - 1 : 0x3fffffff;
-        hi[a] = live ? cen_node[a] + 1 : -0x3fffffff;
+        r[a] = live ? cen_node[a] - 1 : 0x3fffffff;
+        r[3 + a] = live ? cen_node[a] + 1 : -0x3fffffff;
+        r[6 + a] = vb[a];
+        r[9 + a] = vb[3 + a];
     }
+    if (fold)
+        for (int q = threadIdx.x + blockDim.x; q < B.nblk_v; q += blockDim.x) {
+            const int* e = P.vbox + 6LL * (B.blk_v0 + q);
+            for (int a = 0; a < 3; ++a) { r[6 + a] = min(r[6 + a], e[a]); r[9 + a] = max(r[9 + a], e[3 + a]); }
+        }
     for (int o = 32; o >= 1; o >>= 1)
         for (int a = 0; a < 3; ++a) {
-            lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
-            hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
+            r[a] = min(r[a], __shfl_xor(r[a], o, 64));
+            r[3 + a] = max(r[3 + a], __shfl_xor(r[3 + a], o, 64));
+            if (fold) {
+                r[6 + a] = min(r[6 + a], __shfl_xor(r[6 + a], o, 64));
+                r[9 + a] = max(r[9 + a], __shfl_xor(r[9 + a], o, 64));
+            }
         }
     const int wave = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0)
-        for (int a = 0; a < 3; ++a) { s_box[wave][a] = lo[a]; s_box[wave][3 + a] = hi[a]; }
+        for (int i = 0; i < 12; ++i) s_box[wave][i] = r[i];
     for (int i = threadIdx.x; i < 3 * SPREAD_LDS_NODES; i += blockDim.x) (&s_acc[0][0])[i] = 0;
     __syncthreads();
-    int o[3], w[3];
+    int o[3], w[3], bmin[3], bmax[3];
     long long vol = 1;
     for (int a = 0; a < 3; ++a) {
         int l = s_box[0][a], h = s_box[0][3 + a];
-        for (int q = 1; q < 4; ++q) { l = min(l, s_box[q][a]); h = max(h, s_box[q][3 + a]); }
+        bmin[a] = s_box[0][6 + a];
+        bmax[a] = s_box[0][9 + a];
+        for (int q = 1; q < 4; ++q) {
+            l = min(l, s_box[q][a]);
+            h = max(h, s_box[q][3 + a]);
+            bmin[a] = min(bmin[a], s_box[q][6 + a]);
+            bmax[a] = max(bmax[a], s_box[q][9 + a]);
+        }
         o[a] = l;
         w[a] = h >= l ? h - l + 1 : 1;
         vol *= w[a];
     }
+    WinDesc fd = fd_in;
+    if (fold) {
+        fd = window_from_box(J, B, bmin, bmax, err);
+        if (blk == 0 && threadIdx.x == 0) P.fdesc[b] = fd;
+    }
     const bool use_lds = vol <= SPREAD_LDS_NODES;   // uniform over the block
+    if (live) {
 #pragma unroll
-    for (int sn = 0; sn < MLS_NODES; ++sn) {
-        if (wl[sn] < 0) continue;
-        if (use_lds) {
-            const int k = lane + GROUP * sn;
-            const int li = (cen_node[0] + k % 3 - 1 - o[0]) +
-                           w[0] * ((cen_node[1] + (k / 3) % 3 - 1 - o[1]) + w[1] * (cen_node[2] + k / 9 - 1 - o[2]));
-            for (int c = 0; c < 3; ++c)
-                if (fx[sn][c]) atomicAdd((unsigned long long*)&s_acc[c][li], (unsigned long long)fx[sn][c]);
-        } else {
-            for (int c = 0; c < 3; ++c)
-                if (fx[sn][c]) atomicAdd(fw0 + c * capn + wl[sn], (unsigned long long)fx[sn][c]);
+        for (int sn = 0; sn < MLS_NODES; ++sn) {
+            if (!m.active[sn]) continue;
+            const long long l = win_index(J, fd, m.gx[sn], m.gy[sn], m.gz[sn]);
+            if (l < 0) {
+                err |= FLAG_WINDOW;
+                continue;
+            }
+            if (use_lds) {
+                const int k = lane + GROUP * sn;
+                const int li = (cen_node[0] + k % 3 - 1 - o[0]) +
+                               w[0] * ((cen_node[1] + (k / 3) % 3 - 1 - o[1]) + w[1] * (cen_node[2] + k / 9 - 1 - o[2]));
+                for (int c = 0; c < 3; ++c)
+                    if (fx[sn][c]) atomicAdd((unsigned long long*)&s_acc[c][li], (unsigned long long)fx[sn][c]);
+            } else {
+                for (int c = 0; c < 3; ++c)
+                    if (fx[sn][c]) atomicAdd(fw0 + c * capn + l, (unsigned long long)fx[sn][c]);
+            }
         }
     }
     if (!use_lds) return;
@@ -421,10 +477,20 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
     const int t = blk * MLS_PER_BLOCK + grp;
     const bool live = t < B.nt;
     __shared__ double vol[MLS_PER_BLOCK];
-    __shared__ int sbox[6];
     int err = 0;
-    // triangle geometry at x^n and the desired velocity inputs, loaded before the window fold
-    // below so that their latency overlaps it
+    // everything this block reads before its MLS work is loaded first, so that the latencies
+    // overlap: the vertex-block boxes of x^n (fold) or the published window, the triangle's
+    // vertices and the desired-velocity inputs
+    int vb[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -0x7fffffff, -0x7fffffff, -0x7fffffff};
+    WinDesc fd_pub = {};
+    if (fold) {
+        if ((int)threadIdx.x < B.nblk_v) {
+            const int* e = P.vbox + 6LL * (B.blk_v0 + threadIdx.x);
+            for (int i = 0; i < 6; ++i) vb[i] = e[i];
+        }
+    } else {
+        fd_pub = P.fdesc[b];
+    }
     double xa[3] = {0, 0, 0}, xb_[3] = {0, 0, 0}, xc[3] = {0, 0, 0}, Ub[3] = {0, 0, 0};
     if (live) {
         const int* tv = P.tri + 3 * (B.t0 + t);
@@ -436,37 +502,10 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
                 Ub[a] = (P.uv[3 * (B.v0 + tv[0]) + a] + P.uv[3 * (B.v0 + tv[1]) + a] +
                          P.uv[3 * (B.v0 + tv[2]) + a]) * (1.0 / 3.0);
     }
-    // this step's force window.  fold: the first wave folds the integer boxes the vertex
-    // blocks wrote for x^n (min / max, order independent); every block derives the same
-    // descriptor and block 0 publishes it for the sweep and the moments.  Otherwise the window
-    // kernel of the previous step has published it already.
-    WinDesc fd;
-    if (fold) {
-        if (threadIdx.x < 64) {
-            int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
-            for (int q = threadIdx.x; q < B.nblk_v; q += 64) {
-                const int* vb = P.vbox + 6LL * (B.blk_v0 + q);
-                for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], vb[a]); hi[a] = max(hi[a], vb[3 + a]); }
-            }
-            for (int o = 32; o >= 1; o >>= 1)
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
-                    hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
-                }
-            if (threadIdx.x == 0)
-                for (int a = 0; a < 3; ++a) { sbox[a] = lo[a]; sbox[3 + a] = hi[a]; }
-        }
-        __syncthreads();
-        const int bmin[3] = {sbox[0], sbox[1], sbox[2]}, bmax[3] = {sbox[3], sbox[4], sbox[5]};
-        fd = window_from_box(J, B, bmin, bmax, err);
-        if (blk == 0 && threadIdx.x == 0) P.fdesc[b] = fd;
-    } else {
-        fd = P.fdesc[b];
-    }
     double Vt = 0.0;
     int cen_node[3] = {0, 0, 0};               // node nearest to the centroid (unwrapped)
-    long long wl[MLS_NODES] = {-1, -1};        // window index of each stencil node, -1 if none
-    long long fx[MLS_NODES][3];                // its fixed-point force contribution
+    long long fx[MLS_NODES][3] = {};           // fixed-point force of each stencil node
+    MlsLane m;
     if (live) {
         double cen[3], ab[3], ac[3], N[3];
         for (int a = 0; a < 3; ++a) {
@@ -489,7 +528,6 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
             cross3(pb, pc, bc);
             Vt = dot3(pa, bc) * (1.0 / 6.0);
         }
-        MlsLane m;
         mls_setup(J, cen, B.rw2, lane, m, err);
         for (int a = 0; a < 3; ++a) cen_node[a] = (int)floor(cen[a] + 0.5);
         float4 mom[MLS_NODES];
@@ -508,20 +546,14 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
         // F_l = (U_b - U*) / dt, spread with c_l = A_l h (Eq. bodyforce), as int64 fixed point
 #pragma unroll
         for (int sn = 0; sn < MLS_NODES; ++sn) {
-            fx[sn][0] = fx[sn][1] = fx[sn][2] = 0;
             if (!m.active[sn]) continue;
             const double sc = A * B.shell_h * m.phi[sn];
-            wl[sn] = win_index(J, fd, m.gx[sn], m.gy[sn], m.gz[sn]);
-            if (wl[sn] < 0) {
-                err |= FLAG_WINDOW;
-                continue;
-            }
-            fx[sn][0] = __double2ll_rn(sc * (Ub[0] - U0) * FIX_SCALE);
-            fx[sn][1] = __double2ll_rn(sc * (Ub[1] - U1) * FIX_SCALE);
-            fx[sn][2] = __double2ll_rn(sc * (Ub[2] - U2) * FIX_SCALE);
+            fx[sn][0] = fix_rn(sc * (Ub[0] - U0) * FIX_SCALE);
+            fx[sn][1] = fix_rn(sc * (Ub[1] - U1) * FIX_SCALE);
+            fx[sn][2] = fix_rn(sc * (Ub[2] - U2) * FIX_SCALE);
         }
     }
-    spread_block(P, J, B, fd, live, cen_node, lane, wl, fx);
+    spread_block(P, J, B, b, blk, fold != 0, vb, fd_pub, live, cen_node, m, lane, fx, err);
     if (err) atomicOr(P.flags + B.job, err);
     if (B.rigid || B.kv == 0.0) return;
     if (lane == 0) vol[grp] = Vt;
@@ -692,6 +724,14 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
     int bl[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, bh[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
     if (v < B.nv) {
         const long long gv = B.v0 + v;
+        // incidence entries first (lane j holds entry j when the lists fit in a group), so
+        // that the force loads they address go out together with the moment loads
+        const bool one = B.vt_w <= GROUP && B.vh_w <= GROUP;
+        int tl0 = -1, hc0 = -1;
+        if (one) {
+            if (lane < B.vt_w) tl0 = P.vt_list[B.vt_off + (long long)v * B.vt_w + lane];
+            if (!B.rigid && lane < B.vh_w) hc0 = P.vh_list[B.vh_off + (long long)v * B.vh_w + lane];
+        }
         double x[3], xn[3];
         load3(P.x + 3 * gv, x);
         // membranes: stencil of the vertex and its moments first, so the load overlaps the
@@ -707,23 +747,31 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         // gathered forces: a third of each incident triangle's probe force, its volume force,
         // the spring and bending forces of every incident hinge; lane j takes entry j
         double f[3] = {0.0, 0.0, 0.0};
-        for (int j = lane; j < B.vt_w; j += GROUP) {
-            const int tl = P.vt_list[B.vt_off + (long long)v * B.vt_w + j];
-            if (tl < 0) continue;
+        auto add_tri = [&](int tl) {
             const long long t = B.t0 + tl;
             for (int a = 0; a < 3; ++a) f[a] += P.fext[3 * t + a] * (1.0 / 3.0);
             if (!B.rigid)
                 for (int a = 0; a < 3; ++a) f[a] += P.fvol[3 * t + a];
-        }
-        if (!B.rigid) {
-            for (int j = lane; j < B.vh_w; j += GROUP) {
-                const int code = P.vh_list[B.vh_off + (long long)v * B.vh_w + j];
-                if (code < 0) continue;
-                const double* fe = P.fedge + 15LL * (B.e0 + (code >> 2));
-                const int role = code & 3;
-                const double sgn = role == 0 ? 1.0 : (role == 1 ? -1.0 : 0.0);
-                for (int a = 0; a < 3; ++a) f[a] += sgn * fe[a] + fe[3 + 3 * role + a];
+        };
+        auto add_hinge = [&](int code) {
+            const double* fe = P.fedge + 15LL * (B.e0 + (code >> 2));
+            const int role = code & 3;
+            const double sgn = role == 0 ? 1.0 : (role == 1 ? -1.0 : 0.0);
+            for (int a = 0; a < 3; ++a) f[a] += sgn * fe[a] + fe[3 + 3 * role + a];
+        };
+        if (one) {
+            if (tl0 >= 0) add_tri(tl0);
+            if (hc0 >= 0) add_hinge(hc0);
+        } else {
+            for (int j = lane; j < B.vt_w; j += GROUP) {
+                const int tl = P.vt_list[B.vt_off + (long long)v * B.vt_w + j];
+                if (tl >= 0) add_tri(tl);
             }
+            if (!B.rigid)
+                for (int j = lane; j < B.vh_w; j += GROUP) {
+                    const int code = P.vh_list[B.vh_off + (long long)v * B.vh_w + j];
+                    if (code >= 0) add_hinge(code);
+                }
         }
         const double F0 = gsum(f[0]), F1 = gsum(f[1]), F2 = gsum(f[2]);
         if (!B.rigid) {

@@ -174,13 +174,19 @@ struct Pools {
 struct SweepShape {
     int block;          // threads per block
     int npt;            // nodes per thread (block-strided)
+    int xcd_chunk;      // tiles an XCD takes per turn (0: dispatch order; -1: chosen by footprint)
 };
+// Chunked XCD order pays while the two population buffers stay in the Infinity Cache (256 MB);
+// beyond it, dispatch order keeps all XCDs streaming the same region.
+constexpr int XCD_CHUNK = 8;
+constexpr long long XCD_CHUNK_MAX_BYTES = 192LL << 20;
 
 // lbib_lattice.hip
 // With ev0/ev1 set, the two events are stamped by the sweep's own dispatch packet (its start
 // and end on the device), not by separate stream commands around it.
 void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int ntiles,
-                  SweepShape shape, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                  SweepShape shape, int xcd_chunk, hipStream_t s, hipEvent_t ev0 = nullptr,
+                  hipEvent_t ev1 = nullptr);
 // nblk_w: total window blocks (each body gets blocks in proportion to its window capacity)
 void launch_window_moments(const Pools& P, int storage, bool from_b, int nblk_w, hipStream_t s);
 void launch_macros(const Pools& P, int storage, bool from_b, int job, long long n, float* out4,

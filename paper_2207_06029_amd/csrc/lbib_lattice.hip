@@ -370,8 +370,17 @@ __device__ __forceinline__ void sweep_node(const Pools& P, const JobDev& J, cons
 }
 
 template <typename S, bool COLLIDE, int NPT>
-__global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b) {
-    const int tile = blockIdx.x;
+__global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b, int xcd_chunk) {
+    // The dispatcher deals consecutive blocks to the 8 XCDs in turn, each with its own L2.
+    // With xcd_chunk = C > 0 the blocks are remapped so that every XCD takes C consecutive
+    // tiles per turn: the rows a tile pulls from its neighbours were mostly just read through
+    // the same L2.  Blocks past the last whole turn keep their own tile (a bijection).
+    const int T = gridDim.x, bid = blockIdx.x;
+    int tile = bid;
+    if (xcd_chunk > 0) {
+        const int span = 8 * xcd_chunk;
+        if (bid < (T / span) * span) tile = (bid / span) * span + (bid & 7) * xcd_chunk + (bid >> 3) % xcd_chunk;
+    }
     const int job = P.tile_job[tile];
     const JobDev& J = P.jobs[job];
     const S* src = (const S*)(a_to_b ? P.popA : P.popB) + J.pop_off;
@@ -385,34 +394,35 @@ __global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b) {
 }
 
 template <typename S, bool C, int NPT>
-static void sweep_n(const Pools& P, bool a_to_b, dim3 grid, dim3 block, hipStream_t s, hipEvent_t ev0,
-                    hipEvent_t ev1) {
+static void sweep_n(const Pools& P, bool a_to_b, int chunk, dim3 grid, dim3 block, hipStream_t s,
+                    hipEvent_t ev0, hipEvent_t ev1) {
     if (ev0 || ev1)
-        hipExtLaunchKernelGGL((k_sweep<S, C, NPT>), grid, block, 0, s, ev0, ev1, 0, P, (int)a_to_b);
+        hipExtLaunchKernelGGL((k_sweep<S, C, NPT>), grid, block, 0, s, ev0, ev1, 0, P, (int)a_to_b, chunk);
     else
-        hipLaunchKernelGGL((k_sweep<S, C, NPT>), grid, block, 0, s, P, (int)a_to_b);
+        hipLaunchKernelGGL((k_sweep<S, C, NPT>), grid, block, 0, s, P, (int)a_to_b, chunk);
 }
 
 template <typename S, bool C>
-static void sweep_t(const Pools& P, bool a_to_b, int ntiles, SweepShape sh, hipStream_t s,
+static void sweep_t(const Pools& P, bool a_to_b, int ntiles, SweepShape sh, int chunk, hipStream_t s,
                     hipEvent_t ev0, hipEvent_t ev1) {
     dim3 grid(ntiles), block(sh.block);
     switch (sh.npt) {
-        case 1: sweep_n<S, C, 1>(P, a_to_b, grid, block, s, ev0, ev1); break;
-        case 2: sweep_n<S, C, 2>(P, a_to_b, grid, block, s, ev0, ev1); break;
-        default: sweep_n<S, C, 4>(P, a_to_b, grid, block, s, ev0, ev1); break;
+        case 1: sweep_n<S, C, 1>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
+        case 2: sweep_n<S, C, 2>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
+        default: sweep_n<S, C, 4>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
     }
 }
 
 void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int ntiles,
-                  SweepShape shape, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                  SweepShape shape, int xcd_chunk, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ntiles <= 0) return;
-    if (storage == 0) collide ? sweep_t<float, true>(P, a_to_b, ntiles, shape, s, ev0, ev1)
-                              : sweep_t<float, false>(P, a_to_b, ntiles, shape, s, ev0, ev1);
-    else if (storage == 1) collide ? sweep_t<__half, true>(P, a_to_b, ntiles, shape, s, ev0, ev1)
-                                   : sweep_t<__half, false>(P, a_to_b, ntiles, shape, s, ev0, ev1);
-    else collide ? sweep_t<__hip_bfloat16, true>(P, a_to_b, ntiles, shape, s, ev0, ev1)
-                 : sweep_t<__hip_bfloat16, false>(P, a_to_b, ntiles, shape, s, ev0, ev1);
+    const int c = xcd_chunk;
+    if (storage == 0) collide ? sweep_t<float, true>(P, a_to_b, ntiles, shape, c, s, ev0, ev1)
+                              : sweep_t<float, false>(P, a_to_b, ntiles, shape, c, s, ev0, ev1);
+    else if (storage == 1) collide ? sweep_t<__half, true>(P, a_to_b, ntiles, shape, c, s, ev0, ev1)
+                                   : sweep_t<__half, false>(P, a_to_b, ntiles, shape, c, s, ev0, ev1);
+    else collide ? sweep_t<__hip_bfloat16, true>(P, a_to_b, ntiles, shape, c, s, ev0, ev1)
+                 : sweep_t<__hip_bfloat16, false>(P, a_to_b, ntiles, shape, c, s, ev0, ev1);
 }
 
 // ---------------------------------------------------------------- window moments
@@ -433,14 +443,15 @@ __global__ void __launch_bounds__(256) k_window_moments(Pools P, int from_b) {
         return;
     }
     if (lb == 0 && threadIdx.x == 0) P.mdesc[b] = d;
-    const long long nw = (long long)d.w[0] * d.w[1] * d.w[2];
+    // window sizes are bounded by the capacity, far below 2^31 nodes: 32-bit index arithmetic
+    const unsigned nw = (unsigned)d.w[0] * d.w[1] * d.w[2];
+    const unsigned w0 = d.w[0], w01 = (unsigned)d.w[0] * d.w[1];
     const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
     const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
-    const long long stride = (long long)B.nblk_w * blockDim.x;
-    for (long long l = (long long)lb * blockDim.x + threadIdx.x; l < nw; l += stride) {
-        const int lx = (int)(l % d.w[0]);
-        const int ly = (int)((l / d.w[0]) % d.w[1]);
-        const int lz = (int)(l / ((long long)d.w[0] * d.w[1]));
+    const unsigned stride = (unsigned)B.nblk_w * blockDim.x;
+    for (unsigned l = (unsigned)lb * blockDim.x + threadIdx.x; l < nw; l += stride) {
+        const unsigned lz = l / w01, rem = l - lz * w01;
+        const unsigned ly = rem / w0, lx = rem - ly * w0;
         int x = d.o[0] + lx, y = d.o[1] + ly, z = d.o[2] + lz;
         if (x >= J.nx) x -= J.nx;
         if (y >= J.ny) y -= J.ny;

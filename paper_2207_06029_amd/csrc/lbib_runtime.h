@@ -68,7 +68,8 @@ struct Batch {
     bool cur_b = false;        // buffer holding the latest post-collision state
     bool primed = false;       // moment windows hold the moments of the current state
     long long step_count = 0;
-    SweepShape shape{256, 1};
+    SweepShape shape{256, 1, -1};
+    int xcd_chunk = 0;        // effective XCD chunk of the current shape and footprint
     bool use_graph = false;
     bool graph_valid = false;
     hipGraph_t graph = nullptr;

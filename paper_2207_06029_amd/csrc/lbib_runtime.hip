@@ -404,11 +404,14 @@ lbib_status Batch::create_lattices(const std::vector<lbib_lattice_desc>& descs, 
 lbib_status Batch::retile() {
     tile_job.clear();
     const long long per = (long long)shape.block * shape.npt;
+    long long pop_bytes = 0;
     for (size_t j = 0; j < jobs.size(); ++j) {
         jobs[j].tile0 = (int)tile_job.size();
         jobs[j].ntiles = (int)((jobs[j].n + per - 1) / per);
         for (int t = 0; t < jobs[j].ntiles; ++t) tile_job.push_back((int)j);
+        pop_bytes += 2LL * Q * (long long)storage_bytes(storage) * jobs[j].n;
     }
+    xcd_chunk = shape.xcd_chunk >= 0 ? shape.xcd_chunk : (pop_bytes <= XCD_CHUNK_MAX_BYTES ? XCD_CHUNK : 0);
     HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, stream));
     if (d_tile_job && tile_cap < tile_job.size()) {
         HIP_TRY(hipStreamSynchronize(stream));
@@ -741,10 +744,10 @@ lbib_status Batch::enqueue_step(bool collide) {
         lbib_status st = next_event(&a);
         if (!st) st = next_event(&b);
         if (st) return st;
-        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, stream, a, b);
+        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, xcd_chunk, stream, a, b);
         sweep_events.push_back({a, b});
     } else {
-        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, stream);
+        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, xcd_chunk, stream);
     }
     cur_b = !cur_b;
     if (bodies) {
