@@ -139,7 +139,7 @@ lbib_status lbib_workspace_bytes(const lbib_lattice_desc* desc, int32_t max_nv, 
     size_t b = 2 * 19 * n * lbib::storage_bytes(desc->storage) + 4096;
     if (max_nv > 0) {
         // mesh state and topology, plus force and moment windows no larger than the lattice
-        b += (size_t)max_nv * 8 * 24 + (size_t)max_nt * 8 * 16 + n * (24 + 16) + (1 << 20);
+        b += (size_t)max_nv * 8 * 32 + (size_t)max_nt * 8 * 16 + n * (24 + 16) + (1 << 20);
     }
     *bytes = b;
     return LBIB_OK;

@@ -14,11 +14,11 @@
 //   (sweep)      collide+stream with the spread force
 //   (moments)    moments of f^{n+1} in the body's window
 //   k_triangles  one group per probe (geometry from the centroid kernel): stresses on f^{n+1}
-//                (Eqs. hydroForP, hydroForNu), volume
-//                force per triangle; rigid bodies: FP64 totals and the velocity / pose update
-//                in the last block
-//   k_vertices   vertex velocity from the fluid, gathered forces, membrane update, integer
-//                bounding box of x^{n+1} for the next step's window
+//                (Eqs. hydroForP, hydroForNu), volume force per triangle; rigid bodies: FP64
+//                totals and the velocity / pose update in the last block.  Blocks of their
+//                own: the fluid velocity at every membrane vertex from f^{n+1}
+//   k_vertices   gathered forces, membrane update with that velocity, integer bounding box
+//                of x^{n+1} for the next step's window
 #include "lbib_internal.h"
 
 namespace lbib {
@@ -565,9 +565,45 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
     if (last_block_reduce(P, B, blk, B.nblk_c, &S.counter_c, &sv, op, 1, &V) && threadIdx.x == 0) S.V = V;
 }
 
+// ---------------------------------------------------------------- vertex velocities
+// Fluid velocity at every membrane vertex from the moments of f^{n+1} (the tentative velocity
+// of Eq. verletPos).  It needs nothing from the probes, so its blocks ride in the probe launch
+// and the vertex kernel only gathers forces and moves the vertices.  One group per vertex.
+__device__ void vertex_velocity_block(const Pools& P, int vb) {
+    const int b = P.blk_body_v[vb];
+    const BodyDev& B = P.bodies[b];
+    if (B.rigid) return;
+    const JobDev& J = P.jobs[B.job];
+    const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
+    const int v = (vb - B.blk_v0) * MLS_PER_BLOCK + grp;
+    if (v >= B.nv) return;
+    const long long gv = B.v0 + v;
+    int err = 0;
+    double x[3];
+    load3(P.x + 3 * gv, x);
+    MlsLane m;
+    float4 mom[MLS_NODES];
+    mls_setup(J, x, B.rw2, lane, m, err);
+    mls_moments(P, J, B, b, m, mom, err);
+    mls_solve(m, B.wq, false, err);
+    const double u0 = group_dot(m.phi, 1, mom, 1), u1 = group_dot(m.phi, 1, mom, 2),
+                 u2 = group_dot(m.phi, 1, mom, 3);
+    if (lane == 0) {
+        P.u0v[3 * gv] = u0;
+        P.u0v[3 * gv + 1] = u1;
+        P.u0v[3 * gv + 2] = u2;
+    }
+    if (err) atomicOr(P.flags + B.job, err);
+}
+
 // ---------------------------------------------------------------- triangles (probes)
 // Group 2k evaluates the outer probe of triangle k of the block, group 2k+1 the inner one.
-__global__ void __launch_bounds__(256) k_triangles(Pools P) {
+// Blocks from nblk_tri on compute the vertex velocities instead.
+__global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
+    if ((int)blockIdx.x >= nblk_tri) {
+        vertex_velocity_block(P, blockIdx.x - nblk_tri);
+        return;
+    }
     const int b = P.blk_body_t[blockIdx.x];
     const BodyDev& B = P.bodies[b];
     const JobDev& J = P.jobs[B.job];
@@ -732,18 +768,9 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
             if (lane < B.vt_w) tl0 = P.vt_list[B.vt_off + (long long)v * B.vt_w + lane];
             if (!B.rigid && lane < B.vh_w) hc0 = P.vh_list[B.vh_off + (long long)v * B.vh_w + lane];
         }
-        double x[3], xn[3];
+        double x[3], xn[3], u0[3] = {0.0, 0.0, 0.0};
         load3(P.x + 3 * gv, x);
-        // membranes: stencil of the vertex and its moments first, so the load overlaps the
-        // force gathers below
-        MlsLane m;
-        float4 mom[MLS_NODES];
-#pragma unroll
-        for (int sn = 0; sn < MLS_NODES; ++sn) mom[sn] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (!B.rigid) {
-            mls_setup(J, x, B.rw2, lane, m, err);
-            mls_moments(P, J, B, b, m, mom, err);
-        }
+        if (!B.rigid) load3(P.u0v + 3 * gv, u0);   // fluid velocity, from the probe launch
         // gathered forces: a third of each incident triangle's probe force, its volume force,
         // the spring and bending forces of every incident hinge; lane j takes entry j
         double f[3] = {0.0, 0.0, 0.0};
@@ -775,10 +802,7 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         }
         const double F0 = gsum(f[0]), F1 = gsum(f[1]), F2 = gsum(f[2]);
         if (!B.rigid) {
-            // tentative velocity: fluid velocity at the vertex from f^{n+1}
-            mls_solve(m, B.wq, false, err);
-            const double u0[3] = {group_dot(m.phi, 1, mom, 1), group_dot(m.phi, 1, mom, 2),
-                                  group_dot(m.phi, 1, mom, 3)};
+            // tentative velocity u0: fluid velocity at the vertex from f^{n+1}
             const double Fv[3] = {F0, F1, F2};
             double un[3];
             for (int a = 0; a < 3; ++a) {
@@ -918,8 +942,9 @@ void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, bool fold, hi
 void launch_windows(const Pools& P, int nbodies, hipStream_t s) {
     if (nbodies > 0) hipLaunchKernelGGL(k_windows, dim3(nbodies), dim3(256), 0, s, P);
 }
-void launch_triangles(const Pools& P, int nblocks, hipStream_t s) {
-    if (nblocks > 0) hipLaunchKernelGGL(k_triangles, dim3(nblocks), dim3(256), 0, s, P);
+void launch_triangles(const Pools& P, int nblk_tri, int nblk_vert, hipStream_t s) {
+    if (nblk_tri + nblk_vert > 0)
+        hipLaunchKernelGGL(k_triangles, dim3(nblk_tri + nblk_vert), dim3(256), 0, s, P, nblk_tri);
 }
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s) {
     if (nblocks > 0) hipLaunchKernelGGL(k_vertices, dim3(nblocks), dim3(256), 0, s, P);

@@ -147,6 +147,7 @@ struct Pools {
     double* xprev;           // [3 nv] x^{n-1}
     double* uv;              // [3 nv] vertex velocity u_v^n
     double* fv;              // [3 nv] last total vertex force
+    double* u0v;             // [3 nv] fluid velocity at each vertex from f^{n+1} (MLS)
     const double* xb;        // [3 nv] rigid rest-frame coordinates
     const int* tri;          // [3 nt] (vertex indices local to the body)
     const int* edge;         // [2 ne]
@@ -205,7 +206,7 @@ void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, bool fold, hi
 void launch_windows(const Pools& P, int nbodies, hipStream_t s);
 // bodies from which the force windows are folded once per body by a kernel of their own
 constexpr int WINDOW_KERNEL_MIN_BODIES = 2;
-void launch_triangles(const Pools& P, int nblocks, hipStream_t s);
+void launch_triangles(const Pools& P, int nblk_tri, int nblk_vert, hipStream_t s);
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s);
 void launch_body_totals(const Pools& P, int body, double* out6, hipStream_t s);
 constexpr int TRI_PER_BLOCK = 8;  // probe kernel: two 16-lane groups (+/- probe) per triangle

@@ -553,6 +553,7 @@ lbib_status Batch::rebuild_bodies() {
     if ((st = upload(arena, uv, &P.uv, stream))) return st;
     std::vector<double> zero(x.size(), 0.0);
     if ((st = upload(arena, zero, &P.fv, stream))) return st;
+    if ((st = upload(arena, zero, &P.u0v, stream))) return st;
     for (size_t i = 0; i < hbodies.size(); ++i)
         if (hbodies[i].has_state && !hbodies[i].fv.empty())
             HIP_TRY(hipMemcpyAsync(P.fv + 3 * bd[i].v0, hbodies[i].fv.data(), sizeof(double) * hbodies[i].fv.size(), hipMemcpyHostToDevice, stream));
@@ -752,7 +753,7 @@ lbib_status Batch::enqueue_step(bool collide) {
     cur_b = !cur_b;
     if (bodies) {
         launch_window_moments(P, storage, cur_b, nblk_w, stream);
-        launch_triangles(P, nblk_t, stream);
+        launch_triangles(P, nblk_t, nblk_v, stream);
         launch_vertices(P, nblk_v, stream);
         if (fold_once) launch_windows(P, nbodies, stream);
     }

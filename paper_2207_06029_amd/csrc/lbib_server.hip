@@ -60,7 +60,7 @@ uint64_t job_bytes(const lbib_lattice_desc& d, int storage, const std::vector<do
         int cap[3];
         lbib::window_capacity(dims, rigid, r, cap);
         const uint64_t w = (uint64_t)cap[0] * cap[1] * cap[2];
-        b += w * 40 + nv * 8 * 24 + (uint64_t)nt * 8 * 16;
+        b += w * 40 + nv * 8 * 32 + (uint64_t)nt * 8 * 16;
     }
     return b;
 }
