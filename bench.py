@@ -37,12 +37,12 @@ PEAK_HBM_GBS = 8000.0
 TIMING_PERIOD = 10
 SWEEP_SOURCES = ("paper_2207_06029_amd/csrc/lbib_lattice.hip", "paper_2207_06029_amd/csrc/lbib_internal.h")
 SWEEP_TRAFFIC = {
-    # FETCH_SIZE 39,414.3 KiB x 2.0 + WRITE_SIZE 77,824.1 KiB x 1.0 per dispatch
-    "prolate128": {"sha256": "60f675167c0f60d0ebd137ebb20aba88eb5625934dd1c1652aa6863a895022d4",
-                   "bytes": 160412365},
-    # FETCH_SIZE 313,575.9 KiB x 2.0 + WRITE_SIZE 622,592.0 KiB x 1.0 per dispatch
-    "prolate256": {"sha256": "60f675167c0f60d0ebd137ebb20aba88eb5625934dd1c1652aa6863a895022d4",
-                   "bytes": 1279737651},
+    # FETCH_SIZE 39,271.8 KiB x 2.0 + WRITE_SIZE 77,824.0 KiB x 1.0 per dispatch
+    "prolate128": {"sha256": "60e51d565ae6a75f384b1053c5abe0c27c0dc76a66b5dfe20d341bb4029bb01c",
+                   "bytes": 160120502},
+    # FETCH_SIZE 313,583.9 KiB x 2.0 + WRITE_SIZE 622,592.0 KiB x 1.0 per dispatch
+    "prolate256": {"sha256": "60e51d565ae6a75f384b1053c5abe0c27c0dc76a66b5dfe20d341bb4029bb01c",
+                   "bytes": 1279754092},
 }
 
 
