@@ -180,6 +180,25 @@ def cavity_spec(n: int, reynolds: float, tau: float = 1.0, storage: int = STORE_
     return LatticeSpec(n, n, n, tau, storage=storage, **lid_cavity(u))
 
 
+# Rigid bodies this many times denser than the fluid, without gravity, stand still to within
+# F t^2 / (2 m): a fixed obstacle for the dynamic immersed boundary.
+FIXED_BODY_MASS_RATIO = 1e9
+
+
+def cavity_sphere_job(n: int, reynolds: float, level: int, tau: float = 1.0,
+                      storage: int = STORE_F32, steps: int = 0) -> "Job":
+    """The lid-driven cavity with a fixed solid sphere of diameter 0.2 L at its centre
+    (Sec. 2.1, second experiment; L = n - 1).  Mesh level chosen by the caller: levels 3, 4
+    and 5 at L = 48, 96 and 192 keep about 4.4 markers per unit area."""
+    lat = cavity_spec(n, reynolds, tau=tau, storage=storage)
+    L = n - 1
+    radius = 0.1 * L
+    c = 0.5 * L
+    xyz, tri = spheroid_mesh(level, (radius, radius, radius), (c, c, c))
+    body = BodySpec(rigid=1, ks0=0.0, kb=0.0, kv=0.0, mass_ratio=FIXED_BODY_MASS_RATIO)
+    return Job(f"cavity_sphere_n{n}", lat, body, xyz, tri, steps, kind="cavity")
+
+
 def square_duct(u_wall: float = 0.0) -> dict:
     """Zou-He walls on the y and z faces, periodic along x; every wall slides along x at u_wall."""
     return dict(bc=(BC_PERIODIC, BC_PERIODIC) + (BC_ZOUHE_VELOCITY,) * 4,
