@@ -374,13 +374,13 @@ __device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, co
             const int* e = P.vbox + 6LL * (B.blk_v0 + q);
             for (int a = 0; a < 3; ++a) { r[6 + a] = min(r[6 + a], e[a]); r[9 + a] = max(r[9 + a], e[3 + a]); }
         }
-    for (int o = 32; o >= 1; o >>= 1)
+    for (int sh = 32; sh >= 1; sh >>= 1)
         for (int a = 0; a < 3; ++a) {
-            r[a] = min(r[a], __shfl_xor(r[a], o, 64));
-            r[3 + a] = max(r[3 + a], __shfl_xor(r[3 + a], o, 64));
+            r[a] = min(r[a], __shfl_xor(r[a], sh, 64));
+            r[3 + a] = max(r[3 + a], __shfl_xor(r[3 + a], sh, 64));
             if (fold) {
-                r[6 + a] = min(r[6 + a], __shfl_xor(r[6 + a], o, 64));
-                r[9 + a] = max(r[9 + a], __shfl_xor(r[9 + a], o, 64));
+                r[6 + a] = min(r[6 + a], __shfl_xor(r[6 + a], sh, 64));
+                r[9 + a] = max(r[9 + a], __shfl_xor(r[9 + a], sh, 64));
             }
         }
     const int wave = threadIdx.x / 64;

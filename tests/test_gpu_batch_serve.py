@@ -135,3 +135,42 @@ def test_server_alone_vs_mix_24_stream_jobs(api):
         x_a, _ = alone.lattice(0).body_state(0)
         np.testing.assert_array_equal(r["xyz"], x_a)
         alone.destroy()
+
+
+def _tune_key(jobs, storage):
+    """The tune cache's key of a job mix: storage, then each lattice shape with its count."""
+    cnt = {}
+    for j in jobs:
+        k = f"{j.lattice.nx}x{j.lattice.ny}x{j.lattice.nz}"
+        cnt[k] = cnt.get(k, 0) + 1
+    return f"s{storage}" + "".join(f";{k}*{v}" for k, v in sorted(cnt.items()))
+
+
+def test_xcd_tile_order_does_not_change_results(api, tmp_path):
+    """The sweep's XCD chunking only reorders tiles: dispatch order and chunks of 8 and 3 give
+    bitwise the same state.  The shapes are forced through the tune cache."""
+    jobs = mixed_jobs(3, 40)
+    key = _tune_key(jobs, I.STORE_F16)
+    states = []
+    for chunk in (0, 8, 3):
+        cache = tmp_path / f"tune{chunk}.txt"
+        cache.write_text(f"{key} 256 1 {chunk}\n")
+        bt = api.Batch(jobs, storage=I.STORE_F16, autotune=True, tune_cache=str(cache))
+        assert bt.launch_shape() == (256, 1)
+        bt.step(40)
+        states.append([state_of(bt.lattice(j)) for j in range(len(jobs))])
+        bt.destroy()
+    for other in states[1:]:
+        for (u_r, x_r), (u_o, x_o) in zip(states[0], other):
+            np.testing.assert_array_equal(u_r, u_o)
+            np.testing.assert_array_equal(x_r, x_o)
+
+
+def test_tune_cache_lines_without_chunk_still_load(api, tmp_path):
+    jobs = mixed_jobs(2, 10)
+    cache = tmp_path / "old.txt"
+    cache.write_text(f"{_tune_key(jobs, I.STORE_F16)} 512 2\n")
+    bt = api.Batch(jobs, storage=I.STORE_F16, autotune=True, tune_cache=str(cache))
+    assert bt.launch_shape() == (512, 2)
+    bt.step(10)
+    bt.sync()
