@@ -9,7 +9,8 @@ update (all HIP kernels of the library).  value = lattice node updates per secon
 the timed steps.  The sweep's average launch duration comes from start/end events stamped by
 every sweep launch's own dispatch packet on the lattice's stream inside the timed region.
 `--workload prolate256` runs the same physics at 256x128x256 (level-5 mesh), a working set
-larger than the Infinity Cache.  `--mode batch` and `--mode serve` run the batched and served
+larger than the Infinity Cache; `--workload settling384` the 96x96x384 closed box with a rigid
+settling sphere in FP16 shifted storage (working set 269 MB).  `--mode batch` and `--mode serve` run the batched and served
 forms (64 capsule jobs; a Poisson stream of capsule and settling jobs).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
@@ -65,9 +66,12 @@ def measured_traffic(workload: str):
 # Plain FP32 workloads: the prolate capsule in shear at 128x64x128 (the headline case) and the
 # same physics at twice the linear size, whose populations (2 x 637 MB) do not fit the 256 MB
 # Infinity Cache.
+# name -> (generator in inputs, its arguments after the seed (None: seeded), description)
 WORKLOADS = {
-    "prolate128": ("prolate_shear", "level-4 mesh (2562 vertices, 5120 markers)"),
-    "prolate256": ("prolate_shear_large", "level-5 mesh (10242 vertices, 20480 markers)"),
+    "prolate128": ("prolate_shear", None, "prolate capsule in shear, level-4 mesh (2562 vertices, 5120 markers)"),
+    "prolate256": ("prolate_shear_large", None, "prolate capsule in shear, level-5 mesh (10242 vertices, 20480 markers)"),
+    "settling384": ("settling_sphere", (1.5, 1), "rigid sphere settling in a closed box, density ratio 1.5, "
+                                                 "level-4 mesh (2562 vertices, 5120 markers)"),
 }
 
 
@@ -287,9 +291,10 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    gen, mesh_text = WORKLOADS[args.workload]
-    job = getattr(I, gen)(args.seed)
+    gen, gen_args, wl_text = WORKLOADS[args.workload]
+    job = getattr(I, gen)(*gen_args) if gen_args is not None else getattr(I, gen)(args.seed)
     spec = job.lattice
+    s_bytes = 4 if spec.storage == I.STORE_F32 else 2
     lat = api.Lattice(spec, stream=stream)
     b = lat.add_body(job.body, job.xyz, job.tri)
     lat.step(args.warmup)
@@ -309,7 +314,7 @@ def main() -> int:
     n = spec.n
     mlups = n * args.steps / wall / 1e6
     sweep_avg_s = sweep_ms / nsweep / 1e3
-    bytes_per_launch = 2 * 19 * 4 * n      # algorithmic: read and write 19 FP32 per node
+    bytes_per_launch = 2 * 19 * s_bytes * n  # algorithmic: read and write 19 stored values per node
     achieved = bytes_per_launch / sweep_avg_s / 1e9
     out = {
         "metric": METRIC,
@@ -322,16 +327,16 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if s_bytes == 4 else "f16-storage/f32-compute",
         "data": "synthetic",
-        "config": {"workload": f"prolate capsule in shear, {spec.nx}x{spec.ny}x{spec.nz} D3Q19, "
-                               f"{mesh_text}, tau={spec.tau:.4f} "
-                               f"(seed {args.seed}), FP32 shifted populations",
+        "config": {"workload": f"{wl_text}, {spec.nx}x{spec.ny}x{spec.nz} D3Q19, tau={spec.tau:.4f}"
+                               + (f" (seed {args.seed})" if gen_args is None else "")
+                               + (", FP32 shifted populations" if s_bytes == 4 else ", FP16 shifted populations"),
                    "lattice": [spec.nx, spec.ny, spec.nz], "markers": int(len(job.tri)), "name": args.workload,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload),
-                     "kernel": "k_sweep<float,collide>",
+                     "kernel": "k_sweep<float,collide>" if s_bytes == 4 else "k_sweep<half,collide>",
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": round(sweep_avg_s * 1e6, 3)},
         "breakdown": {"sweep_us_avg": round(sweep_avg_s * 1e6, 3),
@@ -342,7 +347,7 @@ def main() -> int:
     }
     if args.graph:
         # same job as a one-job batch whose steps replay a captured two-step hipGraph
-        bt = api.Batch([job], storage=I.STORE_F32, use_graph=True, stream=stream)
+        bt = api.Batch([job], storage=spec.storage, use_graph=True, stream=stream)
         bt.step(args.warmup)
         bt.sync()
         torch.cuda.synchronize()
