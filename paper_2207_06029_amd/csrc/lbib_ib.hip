@@ -9,14 +9,16 @@
 // Step order inside the time step n -> n+1:
 //   k_centroids  triangle blocks: force window of this step from the vertex bounding box,
 //                geometry at x^n (kept for the probes), MLS at centroids on moments of f^n,
-//                F_l = U_b - U*, fixed-point spreading into the body's force window, enclosed
-//                volume V^n (k_v != 0); edge blocks: spring and bending forces of every hinge
+//                F_l = U_b - U*, fixed-point spreading into the body's force window, partial
+//                enclosed volumes; edge blocks: spring and bending forces of every hinge
+//   k_fold_bodies (membranes with k_v != 0) volume V^n from the partials
 //   (sweep)      collide+stream with the spread force
 //   (moments)    moments of f^{n+1} in the body's window
 //   k_triangles  one group per probe (geometry from the centroid kernel): stresses on f^{n+1}
 //                (Eqs. hydroForP, hydroForNu), volume force per triangle; rigid bodies: FP64
-//                totals and the velocity / pose update in the last block.  Blocks of their
-//                own: the fluid velocity at every membrane vertex from f^{n+1}
+//                partial force and torque per block.  Blocks of their own: the fluid velocity
+//                at every membrane vertex from f^{n+1}
+//   k_fold_bodies (rigid bodies) FP64 totals and the velocity / pose update
 //   k_vertices   gathered forces, membrane update with that velocity, integer bounding box
 //                of x^{n+1} for the next step's window
 #include "lbib_internal.h"
@@ -42,9 +44,6 @@ __device__ __forceinline__ double gsum(double v) {
     return v;
 }
 
-__device__ __forceinline__ double agent_load(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // One MLS point, per lane of its 16-lane group: lane k owns nodes k and k + 16 (when < 27) of
 // the 3x3x3 block around the nearest node.  mls_setup finds each node, its offset d = x_k - x,
@@ -212,48 +211,35 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-// Deterministic per-body reduction across the blocks of one body.  Thread 0 of every block
-// publishes nval partials (op[i] = 0 sum, 1 min, 2 max); the last block to arrive folds them
-// with all its threads: thread t takes blocks t, t+256, ... in order, then a fixed-shape tree
-// in LDS combines the 256 results.  The order depends only on the body's own block count, so
-// totals are bitwise reproducible and independent of other jobs in the launch.  Returns true
-// in every thread of the last block; out[] is valid in all its threads.
-constexpr int RED_MAX = 9;
+// Deterministic per-body totals.  Every block of a body stores its partial sums (up to six
+// values, in a slot of 16 doubles); one block per body folds them in a later launch, whose
+// boundary makes the partials visible without a per-block device-scope release (each of which
+// would write back an L2).  Thread t takes blocks t, t+256, ... in order, then a fixed-shape
+// tree in LDS combines the 256 results: the order depends only on the body's own block count,
+// so totals are bitwise reproducible and independent of other jobs in the launch.
+constexpr int FOLD_MAX = 6;
 
-__device__ bool last_block_reduce(const Pools& P, const BodyDev& B, int blk, int nblk, int* counter,
-                                  const double* mine, const int* op, int nval, double* out) {
-    __shared__ int s_last;
-    __shared__ double s_red[RED_MAX][256];
-    if (threadIdx.x == 0) {
-        double* slot = P.partial + 16LL * (B.red_slot + blk);
-        for (int i = 0; i < nval; ++i) slot[i] = mine[i];
-        __threadfence();
-        s_last = atomicAdd(counter, 1) == nblk - 1;
-    }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
+__device__ __forceinline__ void store_partials(const Pools& P, const BodyDev& B, int blk, const double* v,
+                                               int nval) {
+    double* slot = P.partial + 16LL * (B.red_slot + blk);
+    for (int i = 0; i < nval; ++i) slot[i] = v[i];
+}
+
+__device__ void fold_partials(const Pools& P, const BodyDev& B, int nblk, int nval, double* out) {
+    __shared__ double s_red[FOLD_MAX][256];
     const int t = threadIdx.x;
     for (int i = 0; i < nval; ++i) {
-        double acc = op[i] == 0 ? 0.0 : (op[i] == 1 ? 1e300 : -1e300);
-        for (int k = t; k < nblk; k += 256) {
-            const double v = agent_load(P.partial + 16LL * (B.red_slot + k) + i);
-            acc = op[i] == 0 ? acc + v : (op[i] == 1 ? fmin(acc, v) : fmax(acc, v));
-        }
+        double acc = 0.0;
+        for (int k = t; k < nblk; k += 256) acc += P.partial[16LL * (B.red_slot + k) + i];
         s_red[i][t] = acc;
     }
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
         if (t < w)
-            for (int i = 0; i < nval; ++i) {
-                const double a = s_red[i][t], b = s_red[i][t + w];
-                s_red[i][t] = op[i] == 0 ? a + b : (op[i] == 1 ? fmin(a, b) : fmax(a, b));
-            }
+            for (int i = 0; i < nval; ++i) s_red[i][t] += s_red[i][t + w];
         __syncthreads();
     }
     for (int i = 0; i < nval; ++i) out[i] = s_red[i][0];
-    if (t == 0) *counter = 0;
-    return true;
 }
 
 // ---------------------------------------------------------------- window of a step
@@ -560,9 +546,7 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
     __syncthreads();
     double sv = 0.0;
     for (int g = 0; g < MLS_PER_BLOCK; ++g) sv += vol[g];
-    const int op[1] = {0};
-    double V;
-    if (last_block_reduce(P, B, blk, B.nblk_c, &S.counter_c, &sv, op, 1, &V) && threadIdx.x == 0) S.V = V;
+    if (threadIdx.x == 0) store_partials(P, B, blk, &sv, 1);   // folded into V by k_fold_bodies
 }
 
 // ---------------------------------------------------------------- vertex velocities
@@ -673,13 +657,15 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
     if (side == 0 && lane == 0)
         for (int i = 0; i < 3; ++i) { red[k][i] = Ft[i]; red[k][3 + i] = Mt[i]; }
     __syncthreads();
+    if (threadIdx.x != 0) return;
     double part[6] = {0, 0, 0, 0, 0, 0};
     for (int g = 0; g < TRI_PER_BLOCK; ++g)
         for (int i = 0; i < 6; ++i) part[i] += red[g][i];
-    const int op[6] = {0, 0, 0, 0, 0, 0};
-    double tot[6];
-    if (!last_block_reduce(P, B, blk, B.nblk_t, &S.counter_t, part, op, 6, tot)) return;
-    if (threadIdx.x != 0) return;
+    store_partials(P, B, blk, part, 6);   // folded, with the pose update, by k_fold_bodies
+}
+
+// Rigid body, Eqs. (linearVelRig), (angularVelRig), from the FP64 totals tot = (F, M).
+__device__ void rigid_update(const Pools& P, const BodyDev& B, BodyState& S, const double tot[6]) {
     for (int i = 0; i < 3; ++i) { S.F[i] = tot[i]; S.M[i] = tot[3 + i]; }
     // Rigid body, Eqs. (linearVelRig), (angularVelRig): udot = F/m with net weight (m - V0) g,
     // omegadot = I_w^{-1} M with I_w = R I R^T.
@@ -741,6 +727,22 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
     for (int i = 0; i < 9; ++i) { S.R[i] = Rn[i]; fin = fin && isfinite(Rn[i]); }
     for (int i = 0; i < 3; ++i) fin = fin && isfinite(S.X[i]) && isfinite(un[i]) && isfinite(wn[i]);
     if (!fin) atomicOr(P.flags + B.job, FLAG_NONFINITE);
+}
+
+// ---------------------------------------------------------------- per-body totals
+// One block per body.  mode 0 (after the centroid kernel): enclosed volume V^n of membranes
+// with a volume penalty; mode 1 (after the probe kernel): hydrodynamic totals and the velocity
+// / pose update of rigid bodies.  Other bodies return at once.
+__global__ void __launch_bounds__(256) k_fold_bodies(Pools P, int mode) {
+    const int b = blockIdx.x;
+    const BodyDev& B = P.bodies[b];
+    if (mode == 0 ? (B.rigid || B.kv == 0.0) : !B.rigid) return;
+    BodyState& S = P.bstate[b];
+    double tot[FOLD_MAX];
+    fold_partials(P, B, mode == 0 ? B.nblk_c : B.nblk_t, mode == 0 ? 1 : 6, tot);
+    if (threadIdx.x != 0) return;
+    if (mode == 0) S.V = tot[0];
+    else rigid_update(P, B, S, tot);
 }
 
 // ---------------------------------------------------------------- vertices
@@ -942,6 +944,10 @@ void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, bool fold, hi
 void launch_windows(const Pools& P, int nbodies, hipStream_t s) {
     if (nbodies > 0) hipLaunchKernelGGL(k_windows, dim3(nbodies), dim3(256), 0, s, P);
 }
+void launch_fold_bodies(const Pools& P, int nbodies, int mode, hipStream_t s) {
+    if (nbodies > 0) hipLaunchKernelGGL(k_fold_bodies, dim3(nbodies), dim3(256), 0, s, P, mode);
+}
+
 void launch_triangles(const Pools& P, int nblk_tri, int nblk_vert, hipStream_t s) {
     if (nblk_tri + nblk_vert > 0)
         hipLaunchKernelGGL(k_triangles, dim3(nblk_tri + nblk_vert), dim3(256), 0, s, P, nblk_tri);

@@ -128,7 +128,7 @@ struct BodyState {
     double F[3], M[3]; // rigid bodies: hydrodynamic force / torque totals of the last step
     // rigid body
     double X[3], R[9], u[3], u1[3], om[3], om1[3];
-    int counter_c, counter_t, pad0, pad1;
+    int pad[4];
 };
 
 // All device pools of one batch.  Kernels take this by value.
@@ -207,6 +207,8 @@ void launch_windows(const Pools& P, int nbodies, hipStream_t s);
 // bodies from which the force windows are folded once per body by a kernel of their own
 constexpr int WINDOW_KERNEL_MIN_BODIES = 2;
 void launch_triangles(const Pools& P, int nblk_tri, int nblk_vert, hipStream_t s);
+// mode 0: volumes of membranes with a volume penalty; mode 1: rigid totals and pose update
+void launch_fold_bodies(const Pools& P, int nbodies, int mode, hipStream_t s);
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s);
 void launch_body_totals(const Pools& P, int body, double* out6, hipStream_t s);
 constexpr int TRI_PER_BLOCK = 8;  // probe kernel: two 16-lane groups (+/- probe) per triangle

@@ -531,7 +531,6 @@ lbib_status Batch::rebuild_bodies() {
             for (int k = 0; k < 9; ++k) S.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
             for (int a = 0; a < 3; ++a) S.X[a] = h.X0[a];
         }
-        S.counter_c = S.counter_t = 0;
         // every vertex block starts with the box of the current positions
         for (int k = 0; k < nbv; ++k) {
             for (int a = 0; a < 3; ++a) vbox.push_back((int)std::floor(lo[a]));
@@ -542,6 +541,11 @@ lbib_status Batch::rebuild_bodies() {
         if (over) return fail(LBIB_EDOMAIN, "body does not fit its window");
     }
     nbodies = (int)hbodies.size();
+    any_rigid = any_volume = false;
+    for (const HostBody& h : hbodies) {
+        if (h.desc.rigid) any_rigid = true;
+        else if (h.desc.kv != 0.0) any_volume = true;
+    }
     if ((st = upload(arena, bd, (BodyDev**)&P.bodies, stream))) return st;
     if ((st = upload(arena, bc, (int**)&P.blk_body_c, stream))) return st;
     if ((st = upload(arena, be, (int**)&P.blk_body_e, stream))) return st;
@@ -739,7 +743,10 @@ lbib_status Batch::prime() {
 lbib_status Batch::enqueue_step(bool collide) {
     const bool bodies = collide && nbodies > 0;
     const bool fold_once = nbodies >= WINDOW_KERNEL_MIN_BODIES;
-    if (bodies) launch_centroids(P, nblk_c, nblk_e, !fold_once, stream);
+    if (bodies) {
+        launch_centroids(P, nblk_c, nblk_e, !fold_once, stream);
+        if (any_volume) launch_fold_bodies(P, nbodies, 0, stream);
+    }
     if (timing && sweep_seq++ % timing_period == 0) {
         hipEvent_t a, b;
         lbib_status st = next_event(&a);
@@ -754,6 +761,7 @@ lbib_status Batch::enqueue_step(bool collide) {
     if (bodies) {
         launch_window_moments(P, storage, cur_b, nblk_w, stream);
         launch_triangles(P, nblk_t, nblk_v, stream);
+        if (any_rigid) launch_fold_bodies(P, nbodies, 1, stream);
         launch_vertices(P, nblk_v, stream);
         if (fold_once) launch_windows(P, nbodies, stream);
     }
