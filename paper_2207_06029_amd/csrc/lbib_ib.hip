@@ -225,21 +225,36 @@ __device__ __forceinline__ void store_partials(const Pools& P, const BodyDev& B,
     for (int i = 0; i < nval; ++i) slot[i] = v[i];
 }
 
-__device__ void fold_partials(const Pools& P, const BodyDev& B, int nblk, int nval, double* out) {
+template <int NVAL>
+__device__ void fold_partials(const Pools& P, const BodyDev& B, int nblk, double* out) {
     __shared__ double s_red[FOLD_MAX][256];
     const int t = threadIdx.x;
-    for (int i = 0; i < nval; ++i) {
-        double acc = 0.0;
-        for (int k = t; k < nblk; k += 256) acc += P.partial[16LL * (B.red_slot + k) + i];
-        s_red[i][t] = acc;
+    double acc[NVAL];
+    for (int i = 0; i < NVAL; ++i) acc[i] = 0.0;
+    // four slots per round, loaded together; summed in ascending block order
+    for (int k0 = t; k0 < nblk; k0 += 4 * 256) {
+        double v[4][NVAL];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * 256;
+            const double* slot = P.partial + 16LL * (B.red_slot + (k < nblk ? k : 0));
+#pragma unroll
+            for (int i = 0; i < NVAL; ++i) v[u][i] = slot[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k0 + u * 256 < nblk)
+#pragma unroll
+                for (int i = 0; i < NVAL; ++i) acc[i] += v[u][i];
     }
+    for (int i = 0; i < NVAL; ++i) s_red[i][t] = acc[i];
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
         if (t < w)
-            for (int i = 0; i < nval; ++i) s_red[i][t] += s_red[i][t + w];
+            for (int i = 0; i < NVAL; ++i) s_red[i][t] += s_red[i][t + w];
         __syncthreads();
     }
-    for (int i = 0; i < nval; ++i) out[i] = s_red[i][0];
+    for (int i = 0; i < NVAL; ++i) out[i] = s_red[i][0];
 }
 
 // ---------------------------------------------------------------- window of a step
@@ -737,12 +752,16 @@ __global__ void __launch_bounds__(256) k_fold_bodies(Pools P, int mode) {
     const int b = blockIdx.x;
     const BodyDev& B = P.bodies[b];
     if (mode == 0 ? (B.rigid || B.kv == 0.0) : !B.rigid) return;
-    BodyState& S = P.bstate[b];
     double tot[FOLD_MAX];
-    fold_partials(P, B, mode == 0 ? B.nblk_c : B.nblk_t, mode == 0 ? 1 : 6, tot);
+    if (mode == 0) fold_partials<1>(P, B, B.nblk_c, tot);
+    else fold_partials<6>(P, B, B.nblk_t, tot);
     if (threadIdx.x != 0) return;
-    if (mode == 0) S.V = tot[0];
-    else rigid_update(P, B, S, tot);
+    if (mode == 0) { P.bstate[b].V = tot[0]; return; }
+    // the state and the body constants are read into registers at once and stored once
+    const BodyDev Bc = B;
+    BodyState S = P.bstate[b];
+    rigid_update(P, Bc, S, tot);
+    P.bstate[b] = S;
 }
 
 // ---------------------------------------------------------------- vertices
