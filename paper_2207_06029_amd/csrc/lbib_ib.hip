@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
     if ((int)blockIdx.x >= nblk_tri) {
         // edge blocks: one thread per hinge of a membrane
         const int eb = blockIdx.x - nblk_tri;
-        const int b = P.blk_body_e[eb];
+        const int b = block_body(P, P.blk_body_e, eb);
         const BodyDev& B = P.bodies[b];
         const int e = (eb - B.blk_e0) * 256 + threadIdx.x;
         if (e >= B.ne) return;
@@ -469,9 +469,9 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
         for (int i = 0; i < 15; ++i) o[i] = f[i];
         return;
     }
-    const int b = P.blk_body_c[blockIdx.x];
+    const int b = block_body(P, P.blk_body_c, blockIdx.x);
     const BodyDev& B = P.bodies[b];
-    const JobDev& J = P.jobs[B.job];
+    const JobDev& J = body_job(P, B);
     BodyState& S = P.bstate[b];
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_c0;
@@ -569,10 +569,10 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
 // of Eq. verletPos).  It needs nothing from the probes, so its blocks ride in the probe launch
 // and the vertex kernel only gathers forces and moves the vertices.  One group per vertex.
 __device__ void vertex_velocity_block(const Pools& P, int vb) {
-    const int b = P.blk_body_v[vb];
+    const int b = block_body(P, P.blk_body_v, vb);
     const BodyDev& B = P.bodies[b];
     if (B.rigid) return;
-    const JobDev& J = P.jobs[B.job];
+    const JobDev& J = body_job(P, B);
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int v = (vb - B.blk_v0) * MLS_PER_BLOCK + grp;
     if (v >= B.nv) return;
@@ -603,9 +603,9 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
         vertex_velocity_block(P, blockIdx.x - nblk_tri);
         return;
     }
-    const int b = P.blk_body_t[blockIdx.x];
+    const int b = block_body(P, P.blk_body_t, blockIdx.x);
     const BodyDev& B = P.bodies[b];
-    const JobDev& J = P.jobs[B.job];
+    const JobDev& J = body_job(P, B);
     BodyState& S = P.bstate[b];
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_t0;
@@ -769,9 +769,9 @@ __device__ __forceinline__ int box_lo(double v) { return (int)floor(fmin(fmax(v,
 __device__ __forceinline__ int box_hi(double v) { return (int)ceil(fmin(fmax(v, -1e7), 1e7)); }
 
 __global__ void __launch_bounds__(256) k_vertices(Pools P) {
-    const int b = P.blk_body_v[blockIdx.x];
+    const int b = block_body(P, P.blk_body_v, blockIdx.x);
     const BodyDev& B = P.bodies[b];
-    const JobDev& J = P.jobs[B.job];
+    const JobDev& J = body_job(P, B);
     BodyState& S = P.bstate[b];
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_v0;

@@ -169,7 +169,18 @@ struct Pools {
     double* partial;         // block partial sums (16 doubles per block)
     int* vbox;               // [6 per vertex block] integer box (floor min, ceil max) of x^{n+1}
     int* flags;              // per job
+    int solo_job;            // job of the only body when the batch holds one body, else -1
 };
+
+// Body of a marker-kernel block, and its job.  With a single body both are known from the
+// kernel arguments, so the body and job records load at once instead of after the block table
+// and after each other (each a round trip beyond the L2 the sweep has just streamed through).
+__device__ __forceinline__ int block_body(const Pools& P, const int* table, int blk) {
+    return P.solo_job >= 0 ? 0 : table[blk];
+}
+__device__ __forceinline__ const JobDev& body_job(const Pools& P, const BodyDev& B) {
+    return P.jobs[P.solo_job >= 0 ? P.solo_job : B.job];
+}
 
 // ---------------------------------------------------------------- launchers
 struct SweepShape {

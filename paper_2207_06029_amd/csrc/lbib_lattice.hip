@@ -432,9 +432,9 @@ template <typename S>
 __global__ void __launch_bounds__(256) k_window_moments(Pools P, int from_b) {
     // blocks of a body are proportional to its window capacity; they stride over the current
     // window, which is usually far smaller than the capacity
-    const int b = P.blk_body_w[blockIdx.x];
+    const int b = block_body(P, P.blk_body_w, blockIdx.x);
     const BodyDev& B = P.bodies[b];
-    const JobDev& J = P.jobs[B.job];
+    const JobDev& J = body_job(P, B);
     const int lb = blockIdx.x - B.blk_w0;
     const WinDesc d = P.fdesc[b];
     const int dims[3] = {J.nx, J.ny, J.nz};

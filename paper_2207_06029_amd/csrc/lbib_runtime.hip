@@ -541,6 +541,7 @@ lbib_status Batch::rebuild_bodies() {
         if (over) return fail(LBIB_EDOMAIN, "body does not fit its window");
     }
     nbodies = (int)hbodies.size();
+    P.solo_job = nbodies == 1 ? hbodies[0].job : -1;
     any_rigid = any_volume = false;
     for (const HostBody& h : hbodies) {
         if (h.desc.rigid) any_rigid = true;
