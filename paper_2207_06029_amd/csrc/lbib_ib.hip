@@ -176,13 +176,14 @@ __device__ __forceinline__ long long win_index(const JobDev& J, const WinDesc& d
 }
 
 // Moments (rho - 1, u*) of the lane's active stencil nodes from the body's moment window.
-__device__ __forceinline__ void mls_moments(const Pools& P, const JobDev& J, const BodyDev& B, int b,
+// md: the layout of the moment window, which callers load with their other early reads
+__device__ __forceinline__ void mls_moments(const Pools& P, const JobDev& J, const BodyDev& B, const WinDesc& md,
                                             const MlsLane& m, float4 mom[MLS_NODES], int& err) {
 #pragma unroll
     for (int s = 0; s < MLS_NODES; ++s) {
         mom[s] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (!m.active[s]) continue;
-        const long long l = win_index(J, P.mdesc[b], m.gx[s], m.gy[s], m.gz[s]);
+        const long long l = win_index(J, md, m.gx[s], m.gy[s], m.gz[s]);
         if (l < 0) err |= FLAG_WINDOW;
         else mom[s] = P.mwin[B.win_off + l];
     }
@@ -484,6 +485,7 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
     // vertices and the desired-velocity inputs
     int vb[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -0x7fffffff, -0x7fffffff, -0x7fffffff};
     WinDesc fd_pub = {};
+    const WinDesc md = P.mdesc[b];
     if (fold) {
         if ((int)threadIdx.x < B.nblk_v) {
             const int* e = P.vbox + 6LL * (B.blk_v0 + threadIdx.x);
@@ -532,7 +534,7 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
         mls_setup(J, cen, B.rw2, lane, m, err);
         for (int a = 0; a < 3; ++a) cen_node[a] = (int)floor(cen[a] + 0.5);
         float4 mom[MLS_NODES];
-        mls_moments(P, J, B, b, m, mom, err);
+        mls_moments(P, J, B, md, m, mom, err);
         mls_solve(m, B.wq, false, err);
         const double U0 = group_dot(m.phi, 1, mom, 1);
         const double U1 = group_dot(m.phi, 1, mom, 2);
@@ -580,10 +582,11 @@ __device__ void vertex_velocity_block(const Pools& P, int vb) {
     int err = 0;
     double x[3];
     load3(P.x + 3 * gv, x);
+    const WinDesc md = P.mdesc[b];
     MlsLane m;
     float4 mom[MLS_NODES];
     mls_setup(J, x, B.rw2, lane, m, err);
-    mls_moments(P, J, B, b, m, mom, err);
+    mls_moments(P, J, B, md, m, mom, err);
     mls_solve(m, B.wq, false, err);
     const double u0 = group_dot(m.phi, 1, mom, 1), u1 = group_dot(m.phi, 1, mom, 2),
                  u2 = group_dot(m.phi, 1, mom, 3);
@@ -613,6 +616,7 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
     const int t = blk * TRI_PER_BLOCK + k;
     __shared__ double probe[MLS_PER_BLOCK][10];
     __shared__ double red[TRI_PER_BLOCK][6];
+    const WinDesc md = P.mdesc[b];
     int err = 0;
     double cen[3] = {0, 0, 0}, N[3] = {0, 0, 0}, nrm[3] = {0, 0, 0}, A = 0.0;
     if (t < B.nt) {
@@ -628,7 +632,7 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
         MlsLane m;
         mls_setup(J, xp, B.rw2, lane, m, err);
         float4 mom[MLS_NODES];
-        mls_moments(P, J, B, b, m, mom, err);
+        mls_moments(P, J, B, md, m, mom, err);
         mls_solve(m, B.wq, true, err);
         // interpolated rho - 1 and the gradient rows of u* (diffuse derivatives)
         double v[10];
