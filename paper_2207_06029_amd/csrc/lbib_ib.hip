@@ -456,12 +456,13 @@ __device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, co
 }
 
 // ---------------------------------------------------------------- centroids (+ hinges)
+template <bool SOLO>
 __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fold) {
     if ((int)blockIdx.x >= nblk_tri) {
         // edge blocks: one thread per hinge of a membrane
         const int eb = blockIdx.x - nblk_tri;
-        const int b = block_body(P, P.blk_body_e, eb);
-        const BodyDev& B = P.bodies[b];
+        const int b = block_body<SOLO>(P, P.blk_body_e, eb);
+        const BodyDev& B = body_of<SOLO>(P, b);
         const int e = (eb - B.blk_e0) * 256 + threadIdx.x;
         if (e >= B.ne) return;
         double f[15];
@@ -470,9 +471,9 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
         for (int i = 0; i < 15; ++i) o[i] = f[i];
         return;
     }
-    const int b = block_body(P, P.blk_body_c, blockIdx.x);
-    const BodyDev& B = P.bodies[b];
-    const JobDev& J = body_job(P, B);
+    const int b = block_body<SOLO>(P, P.blk_body_c, blockIdx.x);
+    const BodyDev& B = body_of<SOLO>(P, b);
+    const JobDev& J = body_job<SOLO>(P, B);
     BodyState& S = P.bstate[b];
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_c0;
@@ -570,11 +571,12 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
 // Fluid velocity at every membrane vertex from the moments of f^{n+1} (the tentative velocity
 // of Eq. verletPos).  It needs nothing from the probes, so its blocks ride in the probe launch
 // and the vertex kernel only gathers forces and moves the vertices.  One group per vertex.
+template <bool SOLO>
 __device__ void vertex_velocity_block(const Pools& P, int vb) {
-    const int b = block_body(P, P.blk_body_v, vb);
-    const BodyDev& B = P.bodies[b];
+    const int b = block_body<SOLO>(P, P.blk_body_v, vb);
+    const BodyDev& B = body_of<SOLO>(P, b);
     if (B.rigid) return;
-    const JobDev& J = body_job(P, B);
+    const JobDev& J = body_job<SOLO>(P, B);
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int v = (vb - B.blk_v0) * MLS_PER_BLOCK + grp;
     if (v >= B.nv) return;
@@ -601,14 +603,15 @@ __device__ void vertex_velocity_block(const Pools& P, int vb) {
 // ---------------------------------------------------------------- triangles (probes)
 // Group 2k evaluates the outer probe of triangle k of the block, group 2k+1 the inner one.
 // Blocks from nblk_tri on compute the vertex velocities instead.
+template <bool SOLO>
 __global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
     if ((int)blockIdx.x >= nblk_tri) {
-        vertex_velocity_block(P, blockIdx.x - nblk_tri);
+        vertex_velocity_block<SOLO>(P, blockIdx.x - nblk_tri);
         return;
     }
-    const int b = block_body(P, P.blk_body_t, blockIdx.x);
-    const BodyDev& B = P.bodies[b];
-    const JobDev& J = body_job(P, B);
+    const int b = block_body<SOLO>(P, P.blk_body_t, blockIdx.x);
+    const BodyDev& B = body_of<SOLO>(P, b);
+    const JobDev& J = body_job<SOLO>(P, B);
     BodyState& S = P.bstate[b];
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_t0;
@@ -772,10 +775,11 @@ __global__ void __launch_bounds__(256) k_fold_bodies(Pools P, int mode) {
 __device__ __forceinline__ int box_lo(double v) { return (int)floor(fmin(fmax(v, -1e7), 1e7)); }
 __device__ __forceinline__ int box_hi(double v) { return (int)ceil(fmin(fmax(v, -1e7), 1e7)); }
 
+template <bool SOLO>
 __global__ void __launch_bounds__(256) k_vertices(Pools P) {
-    const int b = block_body(P, P.blk_body_v, blockIdx.x);
-    const BodyDev& B = P.bodies[b];
-    const JobDev& J = body_job(P, B);
+    const int b = block_body<SOLO>(P, P.blk_body_v, blockIdx.x);
+    const BodyDev& B = body_of<SOLO>(P, b);
+    const JobDev& J = body_job<SOLO>(P, B);
     BodyState& S = P.bstate[b];
     const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
     const int blk = blockIdx.x - B.blk_v0;
@@ -961,8 +965,9 @@ __global__ void __launch_bounds__(256) k_body_totals(Pools P, int b, double* out
 }
 
 void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, bool fold, hipStream_t s) {
-    if (nblk_tri + nblk_edge > 0)
-        hipLaunchKernelGGL(k_centroids, dim3(nblk_tri + nblk_edge), dim3(256), 0, s, P, nblk_tri, (int)fold);
+    if (!(nblk_tri + nblk_edge > 0)) return;
+    if (P.solo_job >= 0) hipLaunchKernelGGL(k_centroids<true>, dim3(nblk_tri + nblk_edge), dim3(256), 0, s, P, nblk_tri, (int)fold);
+    else hipLaunchKernelGGL(k_centroids<false>, dim3(nblk_tri + nblk_edge), dim3(256), 0, s, P, nblk_tri, (int)fold);
 }
 void launch_windows(const Pools& P, int nbodies, hipStream_t s) {
     if (nbodies > 0) hipLaunchKernelGGL(k_windows, dim3(nbodies), dim3(256), 0, s, P);
@@ -972,11 +977,14 @@ void launch_fold_bodies(const Pools& P, int nbodies, int mode, hipStream_t s) {
 }
 
 void launch_triangles(const Pools& P, int nblk_tri, int nblk_vert, hipStream_t s) {
-    if (nblk_tri + nblk_vert > 0)
-        hipLaunchKernelGGL(k_triangles, dim3(nblk_tri + nblk_vert), dim3(256), 0, s, P, nblk_tri);
+    if (!(nblk_tri + nblk_vert > 0)) return;
+    if (P.solo_job >= 0) hipLaunchKernelGGL(k_triangles<true>, dim3(nblk_tri + nblk_vert), dim3(256), 0, s, P, nblk_tri);
+    else hipLaunchKernelGGL(k_triangles<false>, dim3(nblk_tri + nblk_vert), dim3(256), 0, s, P, nblk_tri);
 }
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s) {
-    if (nblocks > 0) hipLaunchKernelGGL(k_vertices, dim3(nblocks), dim3(256), 0, s, P);
+    if (!(nblocks > 0)) return;
+    if (P.solo_job >= 0) hipLaunchKernelGGL(k_vertices<true>, dim3(nblocks), dim3(256), 0, s, P);
+    else hipLaunchKernelGGL(k_vertices<false>, dim3(nblocks), dim3(256), 0, s, P);
 }
 void launch_body_totals(const Pools& P, int body, double* out6, hipStream_t s) {
     hipLaunchKernelGGL(k_body_totals, dim3(1), dim3(256), 0, s, P, body, out6);

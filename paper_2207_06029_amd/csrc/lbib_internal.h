@@ -170,16 +170,25 @@ struct Pools {
     int* vbox;               // [6 per vertex block] integer box (floor min, ceil max) of x^{n+1}
     int* flags;              // per job
     int solo_job;            // job of the only body when the batch holds one body, else -1
+    BodyDev solo_body;       // that body's record (valid when solo_job >= 0)
 };
 
-// Body of a marker-kernel block, and its job.  With a single body both are known from the
-// kernel arguments, so the body and job records load at once instead of after the block table
-// and after each other (each a round trip beyond the L2 the sweep has just streamed through).
+// Body of a marker-kernel block, its record and its job.  The SOLO instantiations serve a batch
+// with one body: its index, record and job come with the kernel arguments, so the first data
+// loads need no round trip for the block table, the body record or the job record (each one
+// beyond the L2 that the sweep has just streamed through).
+template <bool SOLO>
 __device__ __forceinline__ int block_body(const Pools& P, const int* table, int blk) {
-    return P.solo_job >= 0 ? 0 : table[blk];
+    return SOLO ? 0 : table[blk];
 }
+template <bool SOLO>
+__device__ __forceinline__ const BodyDev& body_of(const Pools& P, int b) {
+    if constexpr (SOLO) return P.solo_body;
+    else return P.bodies[b];
+}
+template <bool SOLO>
 __device__ __forceinline__ const JobDev& body_job(const Pools& P, const BodyDev& B) {
-    return P.jobs[P.solo_job >= 0 ? P.solo_job : B.job];
+    return P.jobs[SOLO ? P.solo_job : B.job];
 }
 
 // ---------------------------------------------------------------- launchers

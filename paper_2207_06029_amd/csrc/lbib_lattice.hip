@@ -428,13 +428,13 @@ void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int nt
 // ---------------------------------------------------------------- window moments
 // For every node of a body's current window: pull the post-streaming state, store
 // (rho - 1, u*) with u* = sum f e / rho, and clear the force window for the next step.
-template <typename S>
+template <typename S, bool SOLO>
 __global__ void __launch_bounds__(256) k_window_moments(Pools P, int from_b) {
     // blocks of a body are proportional to its window capacity; they stride over the current
     // window, which is usually far smaller than the capacity
-    const int b = block_body(P, P.blk_body_w, blockIdx.x);
-    const BodyDev& B = P.bodies[b];
-    const JobDev& J = body_job(P, B);
+    const int b = block_body<SOLO>(P, P.blk_body_w, blockIdx.x);
+    const BodyDev& B = body_of<SOLO>(P, b);
+    const JobDev& J = body_job<SOLO>(P, B);
     const int lb = blockIdx.x - B.blk_w0;
     const WinDesc d = P.fdesc[b];
     const int dims[3] = {J.nx, J.ny, J.nz};
@@ -481,9 +481,17 @@ __global__ void __launch_bounds__(256) k_window_moments(Pools P, int from_b) {
 void launch_window_moments(const Pools& P, int storage, bool from_b, int nblk_w, hipStream_t s) {
     if (nblk_w <= 0) return;
     dim3 grid(nblk_w), block(256);
-    if (storage == 0) hipLaunchKernelGGL(k_window_moments<float>, grid, block, 0, s, P, (int)from_b);
-    else if (storage == 1) hipLaunchKernelGGL(k_window_moments<__half>, grid, block, 0, s, P, (int)from_b);
-    else hipLaunchKernelGGL(k_window_moments<__hip_bfloat16>, grid, block, 0, s, P, (int)from_b);
+    const bool solo = P.solo_job >= 0;
+    if (storage == 0) {
+        if (solo) hipLaunchKernelGGL((k_window_moments<float, true>), grid, block, 0, s, P, (int)from_b);
+        else hipLaunchKernelGGL((k_window_moments<float, false>), grid, block, 0, s, P, (int)from_b);
+    } else if (storage == 1) {
+        if (solo) hipLaunchKernelGGL((k_window_moments<__half, true>), grid, block, 0, s, P, (int)from_b);
+        else hipLaunchKernelGGL((k_window_moments<__half, false>), grid, block, 0, s, P, (int)from_b);
+    } else {
+        if (solo) hipLaunchKernelGGL((k_window_moments<__hip_bfloat16, true>), grid, block, 0, s, P, (int)from_b);
+        else hipLaunchKernelGGL((k_window_moments<__hip_bfloat16, false>), grid, block, 0, s, P, (int)from_b);
+    }
 }
 
 // ---------------------------------------------------------------- getters / setters

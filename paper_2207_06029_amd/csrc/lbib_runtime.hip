@@ -542,6 +542,7 @@ lbib_status Batch::rebuild_bodies() {
     }
     nbodies = (int)hbodies.size();
     P.solo_job = nbodies == 1 ? hbodies[0].job : -1;
+    if (nbodies == 1) P.solo_body = bd[0];
     any_rigid = any_volume = false;
     for (const HostBody& h : hbodies) {
         if (h.desc.rigid) any_rigid = true;
