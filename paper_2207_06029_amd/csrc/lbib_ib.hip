@@ -686,8 +686,9 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
     store_partials(P, B, blk, part, 6);   // folded, with the pose update, by k_fold_bodies
 }
 
-// Rigid body, Eqs. (linearVelRig), (angularVelRig), from the FP64 totals tot = (F, M).
-__device__ void rigid_update(const Pools& P, const BodyDev& B, BodyState& S, const double tot[6]) {
+// Rigid body, Eqs. (linearVelRig), (angularVelRig), from the FP64 totals tot = (F, M).  Returns
+// false for a non-finite or singular state.
+__device__ bool rigid_update(const BodyDev& B, BodyState& S, const double tot[6]) {
     for (int i = 0; i < 3; ++i) { S.F[i] = tot[i]; S.M[i] = tot[3 + i]; }
     // Rigid body, Eqs. (linearVelRig), (angularVelRig): udot = F/m with net weight (m - V0) g,
     // omegadot = I_w^{-1} M with I_w = R I R^T.
@@ -748,7 +749,7 @@ __device__ void rigid_update(const Pools& P, const BodyDev& B, BodyState& S, con
     bool fin = isfinite(det) && det != 0.0;
     for (int i = 0; i < 9; ++i) { S.R[i] = Rn[i]; fin = fin && isfinite(Rn[i]); }
     for (int i = 0; i < 3; ++i) fin = fin && isfinite(S.X[i]) && isfinite(un[i]) && isfinite(wn[i]);
-    if (!fin) atomicOr(P.flags + B.job, FLAG_NONFINITE);
+    return fin;
 }
 
 // ---------------------------------------------------------------- per-body totals
@@ -767,8 +768,9 @@ __global__ void __launch_bounds__(256) k_fold_bodies(Pools P, int mode) {
     // the state and the body constants are read into registers at once and stored once
     const BodyDev Bc = B;
     BodyState S = P.bstate[b];
-    rigid_update(P, Bc, S, tot);
+    const bool fin = rigid_update(Bc, S, tot);
     P.bstate[b] = S;
+    if (!fin) atomicOr(P.flags + Bc.job, FLAG_NONFINITE);
 }
 
 // ---------------------------------------------------------------- vertices
