@@ -253,7 +253,7 @@ def bench_serve(args) -> dict:
             "dtype": "f16-storage/f32-compute", "data": "synthetic", "n_gpus": 1}
 
 
-def main() -> int:
+def make_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
@@ -265,19 +265,24 @@ def main() -> int:
                     help="also time the same steps replayed from a captured hipGraph")
     ap.add_argument("--mode", choices=["plain", "batch", "serve"], default="plain")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="prolate128",
-                    help="plain mode: 128x64x128 (default) or 256x128x256 prolate capsule in shear")
+                    help="plain mode: prolate capsule in shear at 128x64x128 (default) or 256x128x256, "
+                         "or the FP16 rigid sphere settling in a 96x96x384 box")
     ap.add_argument("--serve-window", type=float, default=60.0)
     ap.add_argument("--skip-plain", action="store_true",
                     help="batch mode: time only the batched form (no per-job comparison)")
     ap.add_argument("--sources-sha256", action="store_true",
                     help="print the hash of the sweep's sources and exit")
-    args = ap.parse_args()
+    return ap
+
+
+def main() -> int:
+    args = make_parser().parse_args()
     if args.sources_sha256:
         print(sources_sha256())
         return 0
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
-              "decomposition is a design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
         return 2
     if args.calib_copy:
         calibrate_copy(args.calib_copy, 10)
