@@ -34,6 +34,9 @@ def state_of(lat):
 
 
 def test_batch_alone_vs_mix_bitwise(api):
+    """Each job alone (the single-body kernel instantiations, body record in the kernel
+    arguments) against the same job in a six-body mix (block tables): bit for bit, membranes
+    and the rigid sphere alike."""
     jobs = mixed_jobs()
     steps = 120
     mix = api.Batch(jobs, storage=I.STORE_F16)
