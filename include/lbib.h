@@ -157,6 +157,18 @@ int64_t lbib_step_count(const lbib_lattice* lat);
 
 /* rho[N] and u*[3N] = sum f e / rho (force-free velocity) of the current post-streaming state. */
 lbib_status lbib_get_macros(lbib_lattice* lat, double* rho, double* u);
+/* Allocation-free lbib_get_macros, for callers that cannot allocate device memory (loops
+ * that must not call hipMalloc, harnesses that forbid it).  Same outputs, bit for bit, as
+ * lbib_get_macros: rho[N] and u*[3N] in host memory (either may be NULL), after the same
+ * synchronisation and deferred-error report.  The moments are staged in a fixed device array of
+ * 4 * LBIB_NOALLOC_MAX_NODES doubles (32 MiB) that the library holds on every GPU it runs on
+ * until the process ends; the call allocates neither device nor host memory.  The lattice's
+ * device must be current.  Calls on one GPU share its array: calls that overlapped would race
+ * on it, so the library serialises them per device, and the array keeps the last call's
+ * contents (every call overwrites the entries it reads).  Errors: EINVAL (null handle, more than
+ * LBIB_NOALLOC_MAX_NODES nodes, another device current), EDEVICE, EUNSTABLE, EDOMAIN. */
+#define LBIB_NOALLOC_MAX_NODES 1048576
+lbib_status lbib_get_macros_noalloc(lbib_lattice* lat, double* rho, double* u);
 /* Post-streaming populations f[19N] at the current time level, widened to double. */
 lbib_status lbib_get_populations(lbib_lattice* lat, double* f);
 /* Replace the post-streaming populations (narrowed to the storage form), then apply the wall

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "liblbib.so")
 
 LBIB_OK = 0
+LBIB_NOALLOC_MAX_NODES = 1048576
 STATUS = {0: "LBIB_OK", -1: "LBIB_EINVAL", -2: "LBIB_ENOMEM", -3: "LBIB_EDEVICE",
           -4: "LBIB_EUNSTABLE", -5: "LBIB_EBUSY", -6: "LBIB_ENOENT", -7: "LBIB_EDOMAIN"}
 
@@ -85,6 +86,7 @@ SIGNATURES = {
     "lbib_sync": (ctypes.c_int, [_P]),
     "lbib_step_count": (ctypes.c_int64, [_P]),
     "lbib_get_macros": (ctypes.c_int, [_P, _D, _D]),
+    "lbib_get_macros_noalloc": (ctypes.c_int, [_P, _D, _D]),
     "lbib_get_populations": (ctypes.c_int, [_P, _D]),
     "lbib_set_populations": (ctypes.c_int, [_P, _D]),
     "lbib_body_get_state": (ctypes.c_int, [_P, ctypes.c_int32, _D, _D]),

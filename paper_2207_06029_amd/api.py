@@ -113,6 +113,15 @@ class Lattice:
         L.check(self._lib.lbib_get_macros(self._h, L.dptr(rho), L.dptr(u)))
         return rho, u.reshape(3, self.n)
 
+    def macros_noalloc(self, rho: Optional[np.ndarray] = None, u: Optional[np.ndarray] = None):
+        """lbib_get_macros_noalloc into caller arrays (float64, N and 3N; None skips a field)."""
+        for a, m in ((rho, 1), (u, 3)):
+            if a is not None and (a.dtype != np.float64 or a.size != m * self.n or not a.flags.c_contiguous):
+                raise ValueError("outputs must be C-contiguous float64 arrays of N and 3N entries")
+        L.check(self._lib.lbib_get_macros_noalloc(self._h, None if rho is None else L.dptr(rho),
+                                                  None if u is None else L.dptr(u)))
+        return rho, u
+
     def populations(self):
         f = np.zeros(19 * self.n)
         L.check(self._lib.lbib_get_populations(self._h, L.dptr(f)))

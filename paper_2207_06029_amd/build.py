@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 SO = os.path.join(HERE, "liblbib.so")
-SOURCES = ["lbib_lattice.hip", "lbib_ib.hip", "lbib_runtime.hip", "lbib_api.hip", "lbib_server.hip"]
+SOURCES = ["lbib_lattice.hip", "lbib_ib.hip", "lbib_runtime.hip", "lbib_api.hip", "lbib_server.hip",
+           "lbib_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

@@ -212,6 +212,9 @@ void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int nt
 void launch_window_moments(const Pools& P, int storage, bool from_b, int nblk_w, hipStream_t s);
 void launch_macros(const Pools& P, int storage, bool from_b, int job, long long n, float* out4,
                    hipStream_t s);
+// rho[n] then u*[3n] in double (the host layout of lbib_get_macros), written to out[4n]
+void launch_macros_f64(const Pools& P, int storage, bool from_b, int job, long long n, double* out,
+                       hipStream_t s);
 void launch_get_pops(const Pools& P, int storage, bool from_b, int job, long long n, float* out,
                      hipStream_t s);
 void launch_set_pops(const Pools& P, int storage, bool to_b, int job, long long n,

@@ -495,11 +495,10 @@ void launch_window_moments(const Pools& P, int storage, bool from_b, int nblk_w,
 }
 
 // ---------------------------------------------------------------- getters / setters
+// rho - 1 and the force-free velocity u* = sum f e / rho of the post-streaming state at node k
+// (moments of Eq. eqfunc), in FP32.  Both macro getters use it, so they agree bit for bit.
 template <typename S>
-__global__ void k_macros(Pools P, int from_b, int job, float4* out) {
-    const JobDev& J = P.jobs[job];
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= J.n) return;
+__device__ __forceinline__ float4 node_moments(const Pools& P, const JobDev& J, int from_b, long long k) {
     int x, y, z;
     node_coords(J, k, x, y, z);
     const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
@@ -514,7 +513,29 @@ __global__ void k_macros(Pools P, int from_b, int job, float4* out) {
         jz += cz(i) * g[i];
     }
     const float ir = 1.f / (1.f + drho);
-    out[k] = make_float4(drho, jx * ir, jy * ir, jz * ir);
+    return make_float4(drho, jx * ir, jy * ir, jz * ir);
+}
+
+template <typename S>
+__global__ void k_macros(Pools P, int from_b, int job, float4* out) {
+    const JobDev& J = P.jobs[job];
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= J.n) return;
+    out[k] = node_moments<S>(P, J, from_b, k);
+}
+
+// The same moments widened on the device into the host layout: rho[N] (= 1 + (rho - 1)), then
+// u*[3N], so one copy per field moves them to the caller.
+template <typename S>
+__global__ void k_macros_f64(Pools P, int from_b, int job, double* out) {
+    const JobDev& J = P.jobs[job];
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= J.n) return;
+    const float4 m = node_moments<S>(P, J, from_b, k);
+    out[k] = 1.0 + (double)m.x;
+    out[J.n + k] = (double)m.y;
+    out[2 * J.n + k] = (double)m.z;
+    out[3 * J.n + k] = (double)m.w;
 }
 
 template <typename S>
@@ -604,6 +625,11 @@ void launch_macros(const Pools& P, int storage, bool from_b, int job, long long 
                    hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     LBIB_DISPATCH(storage, k_macros, grid, block, s, P, (int)from_b, job, (float4*)out4);
+}
+void launch_macros_f64(const Pools& P, int storage, bool from_b, int job, long long n, double* out,
+                       hipStream_t s) {
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    LBIB_DISPATCH(storage, k_macros_f64, grid, block, s, P, (int)from_b, job, out);
 }
 void launch_get_pops(const Pools& P, int storage, bool from_b, int job, long long n, float* out,
                      hipStream_t s) {

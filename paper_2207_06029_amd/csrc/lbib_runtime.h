@@ -12,6 +12,8 @@
 namespace lbib {
 
 lbib_status fail(lbib_status code, const std::string& msg);
+// Same, with a message of static storage: records it without allocating.
+lbib_status fail_static(lbib_status code, const char* msg);
 const char* last_error();
 lbib_status check_lattice(const lbib_lattice_desc& d);
 size_t storage_bytes(int storage);
@@ -49,6 +51,7 @@ lbib_status build_body(const lbib_body_desc& d, const double* xyz, int nv, const
 
 struct Batch {
     hipStream_t stream = nullptr;
+    int device = -1;           // HIP device current when the batch was created
     int storage = 0;
     Arena arena;
     size_t mark_used = 0, mark_owned = 0;

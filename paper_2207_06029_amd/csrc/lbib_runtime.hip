@@ -15,11 +15,17 @@
 namespace lbib {
 
 static thread_local std::string g_err;
+static thread_local const char* g_err_static = nullptr;
 lbib_status fail(lbib_status code, const std::string& msg) {
     g_err = msg;
+    g_err_static = nullptr;
     return code;
 }
-const char* last_error() { return g_err.c_str(); }
+lbib_status fail_static(lbib_status code, const char* msg) {
+    g_err_static = msg;
+    return code;
+}
+const char* last_error() { return g_err_static ? g_err_static : g_err.c_str(); }
 
 #define HIP_TRY(expr)                                                                      \
     do {                                                                                   \
@@ -367,6 +373,7 @@ lbib_status Batch::create_lattices(const std::vector<lbib_lattice_desc>& descs, 
                                    const std::vector<char>* skip_init) {
     stream = (hipStream_t)stream_;
     storage = storage_;
+    HIP_TRY(hipGetDevice(&device));
     arena.base = ws;
     arena.cap = ws ? ws_bytes : 0;
     ldesc = descs;
