@@ -34,6 +34,50 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+def build_variant(replacements, out_dir: str, name: str = "variant") -> str:
+    """Compile a copy of the oracle with textual replacements [(old, new), ...] applied (each
+    old text must occur exactly once) into out_dir; for tests that plant a mistake in the
+    oracle and check that a pin catches it.  Returns the library path."""
+    src = open(_SRC).read()
+    for old, new in replacements:
+        if src.count(old) != 1:
+            raise ValueError(f"replacement target found {src.count(old)} times: {old!r}")
+        src = src.replace(old, new)
+    os.makedirs(out_dir, exist_ok=True)
+    c = os.path.join(out_dir, name + ".c")
+    so = os.path.join(out_dir, "lib" + name + ".so")
+    with open(c, "w") as f:
+        f.write(src)
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                           "-ffp-contract=off", "-w", "-I", _HERE, "-o", so, c, "-lm"])
+    return so
+
+
+class use_library:
+    """Context manager: route the module's calls (and lattices created inside) to another
+    build of the oracle, e.g. one from build_variant."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        lib()
+        self.saved = _lib
+        L = ctypes.CDLL(self.path)
+        L.orc_last_error.restype = ctypes.c_char_p
+        L.orc_step_count.restype = ctypes.c_int64
+        L.orc_lattice_create.argtypes = [ctypes.POINTER(_LatticeDesc), ctypes.POINTER(ctypes.c_void_p)]
+        L.orc_lattice_destroy.argtypes = [ctypes.c_void_p]
+        _lib = L
+        return L
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
 class _LatticeDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("tau", ctypes.c_double),
@@ -172,15 +216,20 @@ class Lattice:
         self.nx, self.ny, self.nz = int(spec.nx), int(spec.ny), int(spec.nz)
         self.n = self.nx * self.ny * self.nz
         self.tau = float(spec.tau)
+        self._L = lib()
         h = ctypes.c_void_p()
         d = _lattice_desc(spec)
-        _check(lib().orc_lattice_create(ctypes.byref(d), ctypes.byref(h)))
+        self._check(self._L.orc_lattice_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
         self.bodies = []
 
+    def _check(self, rc: int):
+        if rc != OK:
+            raise OracleError(rc, self._L.orc_last_error().decode())
+
     def close(self):
         if self._h:
-            lib().orc_lattice_destroy(self._h)
+            self._L.orc_lattice_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -193,33 +242,33 @@ class Lattice:
     def init(self, rho=None, u=None):
         r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
         v = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
-        _check(lib().orc_lattice_init(self._h, None if r is None else _p(r),
+        self._check(self._L.orc_lattice_init(self._h, None if r is None else _p(r),
                                       None if v is None else _p(v)))
 
     def set_populations(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
-        _check(lib().orc_set_populations(self._h, _p(f)))
+        self._check(self._L.orc_set_populations(self._h, _p(f)))
 
     def populations(self) -> np.ndarray:
         f = np.zeros(19 * self.n)
-        _check(lib().orc_get_populations(self._h, _p(f)))
+        self._check(self._L.orc_get_populations(self._h, _p(f)))
         return f.reshape(19, self.n)
 
     def macros(self):
         rho = np.zeros(self.n)
         u = np.zeros(3 * self.n)
-        _check(lib().orc_get_macros(self._h, _p(rho), _p(u)))
+        self._check(self._L.orc_get_macros(self._h, _p(rho), _p(u)))
         return rho, u.reshape(3, self.n)
 
     def step(self, n: int = 1):
-        _check(lib().orc_step(self._h, int(n)))
+        self._check(self._L.orc_step(self._h, int(n)))
 
     def stream_only(self, n: int = 1):
-        _check(lib().orc_stream_only(self._h, int(n)))
+        self._check(self._L.orc_stream_only(self._h, int(n)))
 
     @property
     def step_count(self) -> int:
-        return int(lib().orc_step_count(self._h))
+        return int(self._L.orc_step_count(self._h))
 
     # bodies --------------------------------------------------------------
     def add_body(self, spec, xyz, tri) -> int:
@@ -227,25 +276,25 @@ class Lattice:
         tri = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1)
         d = _body_desc(spec)
         bid = ctypes.c_int32()
-        _check(lib().orc_body_add(self._h, ctypes.byref(d), _p(xyz), len(xyz) // 3,
+        self._check(self._L.orc_body_add(self._h, ctypes.byref(d), _p(xyz), len(xyz) // 3,
                                   _p(tri, _I32), len(tri) // 3, ctypes.byref(bid)))
         self.bodies.append(bid.value)
         return bid.value
 
     def counts(self, b: int):
         nv, nt, ne = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().orc_body_counts(self._h, b, ctypes.byref(nv), ctypes.byref(nt), ctypes.byref(ne)))
+        self._check(self._L.orc_body_counts(self._h, b, ctypes.byref(nv), ctypes.byref(nt), ctypes.byref(ne)))
         return nv.value, nt.value, ne.value
 
     def set_velocity(self, b: int, v):
         v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
-        _check(lib().orc_body_set_velocity(self._h, b, _p(v)))
+        self._check(self._L.orc_body_set_velocity(self._h, b, _p(v)))
 
     def body_state(self, b: int):
         nv, _, _ = self.counts(b)
         x = np.zeros(3 * nv)
         v = np.zeros(3 * nv)
-        _check(lib().orc_body_get_state(self._h, b, _p(x), _p(v)))
+        self._check(self._L.orc_body_get_state(self._h, b, _p(x), _p(v)))
         return x.reshape(nv, 3), v.reshape(nv, 3)
 
     def body_forces(self, b: int):
@@ -253,14 +302,14 @@ class Lattice:
         fv = np.zeros(3 * nv)
         F = np.zeros(3)
         M = np.zeros(3)
-        _check(lib().orc_body_get_forces(self._h, b, _p(fv), _p(F), _p(M)))
+        self._check(self._L.orc_body_get_forces(self._h, b, _p(fv), _p(F), _p(M)))
         return fv.reshape(nv, 3), F, M
 
     def topology(self, b: int):
         _, _, ne = self.counts(b)
         e = np.zeros(2 * ne, dtype=np.int32)
         h = np.zeros(4 * ne, dtype=np.int32)
-        _check(lib().orc_body_topology(self._h, b, _p(e, _I32), _p(h, _I32)))
+        self._check(self._L.orc_body_topology(self._h, b, _p(e, _I32), _p(h, _I32)))
         return e.reshape(ne, 2), h.reshape(ne, 4)
 
     def rest(self, b: int):
@@ -268,14 +317,31 @@ class Lattice:
         l0, ks, th0 = np.zeros(ne), np.zeros(ne), np.zeros(ne)
         A0 = np.zeros(nt)
         sc = np.zeros(4)
-        _check(lib().orc_body_rest(self._h, b, _p(l0), _p(ks), _p(th0), _p(A0), _p(sc)))
+        self._check(self._L.orc_body_rest(self._h, b, _p(l0), _p(ks), _p(th0), _p(A0), _p(sc)))
         return dict(l0=l0, ks=ks, theta0=th0, A0=A0, V0=sc[0], S0=sc[1], mv=sc[2], mass=sc[3])
+
+    def set_positions(self, b: int, xyz):
+        """Membrane at rest at xyz (x^n = x^{n-1} = xyz, vertex velocities 0)."""
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1)
+        self._check(self._L.orc_body_set_positions(self._h, b, _p(x)))
+
+    def rigid_state(self, b: int):
+        """Centre X, rotation R (x = X + R x_body), velocity u and angular velocity omega."""
+        X, R, u, om = np.zeros(3), np.zeros(9), np.zeros(3), np.zeros(3)
+        self._check(self._L.orc_body_rigid_state(self._h, b, _p(X), _p(R), _p(u), _p(om)))
+        return X, R.reshape(3, 3), u, om
+
+    def rigid_advance(self, b: int, F, M):
+        """The rigid part of the structure update with hydrodynamic totals F, M given."""
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        M = np.ascontiguousarray(M, dtype=np.float64)
+        self._check(self._L.orc_rigid_advance(self._h, b, _p(F), _p(M)))
 
     def rigid_props(self, b: int):
         X0 = np.zeros(3)
         m = ctypes.c_double()
         I = np.zeros(9)
-        _check(lib().orc_body_rigid_props(self._h, b, _p(X0), ctypes.byref(m), _p(I)))
+        self._check(self._L.orc_body_rigid_props(self._h, b, _p(X0), ctypes.byref(m), _p(I)))
         return X0, m.value, I.reshape(3, 3)
 
     def membrane_forces(self, b: int, xyz=None):
@@ -283,7 +349,7 @@ class Lattice:
         F = np.zeros(3 * nv)
         E = np.zeros(3)
         x = None if xyz is None else np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1)
-        _check(lib().orc_membrane_forces(self._h, b, None if x is None else _p(x), _p(F), _p(E)))
+        self._check(self._L.orc_membrane_forces(self._h, b, None if x is None else _p(x), _p(F), _p(E)))
         return F.reshape(nv, 3), E
 
     def mls(self, x, rw: float = 1.3, alpha: float = 0.3):
@@ -293,7 +359,7 @@ class Lattice:
         phi = np.zeros(27)
         g = np.zeros(81)
         c = ctypes.c_int32()
-        _check(lib().orc_mls(self._h, _p(x), ctypes.c_double(rw), ctypes.c_double(alpha),
+        self._check(self._L.orc_mls(self._h, _p(x), ctypes.c_double(rw), ctypes.c_double(alpha),
                              _p(idx, _I64), _p(d), _p(phi), _p(g), ctypes.byref(c)))
         k = c.value
         return idx[:k].copy(), d[:3 * k].reshape(k, 3).copy(), phi[:k].copy(), g[:3 * k].reshape(k, 3).copy()
@@ -303,11 +369,11 @@ class Lattice:
         flb = np.zeros(3 * self.n)
         U = np.zeros(3 * max(nt_total, 1))
         Fl = np.zeros(3 * max(nt_total, 1))
-        _check(lib().orc_ib_force(self._h, _p(flb), _p(U), _p(Fl)))
+        self._check(self._L.orc_ib_force(self._h, _p(flb), _p(U), _p(Fl)))
         return flb.reshape(3, self.n), U[:3 * nt_total].reshape(-1, 3), Fl[:3 * nt_total].reshape(-1, 3)
 
     def probe_forces(self, b: int):
         _, nt, _ = self.counts(b)
         F = np.zeros(3 * nt)
-        _check(lib().orc_body_probe_forces(self._h, b, _p(F)))
+        self._check(self._L.orc_body_probe_forces(self._h, b, _p(F)))
         return F.reshape(nt, 3)

@@ -50,10 +50,10 @@
  *     the membrane forces no longer move the vertices.
  *   - membrane vertex update (default): position from Eq. verletPos with the interpolated fluid
  *     velocity, vertex velocity = the displacement of that step.  The printed three-stage
- *     update (verletPos, verletVel, verletPos again) is one pass of the fixed-point map
- *     x -> x^n + (3/2 x - 2 x^n + 1/2 x^{n-1}) + a/2, whose slope 3/2 amplifies every mismatch
- *     between the fluid velocity and the vertex history; together with the immersed-boundary
- *     feedback it grows without bound at unit density ratio.  It stays available as
+ *     update (verletPos, verletVel, verletPos again) makes the displacement of a step
+ *     -1/2 of the previous one plus 3/2 u0 + 5/4 a: a period-two mode, which the
+ *     immersed-boundary feedback excites in a sheared capsule (the vertex velocity then flips
+ *     sign every step and grows to several times the flow speed).  It stays available as
  *     ORC_INTEGRATOR_PAPER.
  */
 #include "lbib_oracle.h"
@@ -924,6 +924,18 @@ int orc_body_set_velocity(orc_lattice* L, int32_t id, const double* v) {
     return ORC_OK;
 }
 
+/* A membrane at rest at the given positions (its rest state stays the one of orc_body_add):
+ * x^n = x^{n-1} = xyz, u_v = 0. */
+int orc_body_set_positions(orc_lattice* L, int32_t id, const double* xyz) {
+    if (id < 0 || id >= L->nb || L->b[id]->d.rigid) { set_err("no such membrane"); return ORC_EINVAL; }
+    body_t* b = L->b[id];
+    for (int i = 0; i < 3 * b->nv; ++i) {
+        b->x[i] = b->xprev[i] = xyz[i];
+        b->uv[i] = 0.0;
+    }
+    return ORC_OK;
+}
+
 int orc_body_counts(const orc_lattice* L, int32_t id, int32_t* nv, int32_t* nt, int32_t* ne) {
     if (id < 0 || id >= L->nb) { set_err("no such body"); return ORC_EINVAL; }
     *nv = L->b[id]->nv; *nt = L->b[id]->nt; *ne = L->b[id]->ne;
@@ -1239,6 +1251,66 @@ static int solve3(const double A[9], const double b[3], double x[3]) {
     return 0;
 }
 
+/*
+ * One rigid-body update (Sec. 1.3, rigid objects) from the hydrodynamic totals Ft, Mt of the
+ * step: Eqs. linearVelRig / angularVelRig with udot = F/m, F = Ft + (m - V0) g (buoyancy), and
+ * omegadot = I^-1 Mt, I the body inertia rotated into the current pose (R Ib R^T); then
+ * X += u^{n+1} dt, the pose turned by the rotation vector omega^{n+1} dt (Rodrigues), and the
+ * vertices placed at X + R x_body.
+ */
+static int rigid_advance(body_t* b, const double Ft[3], const double Mt[3]) {
+    double F[3];
+    for (int a = 0; a < 3; ++a) F[a] = Ft[a] + (b->mass - b->V0) * b->d.gravity[a];
+    double Iw[9], tmp[9], Rt[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Rt[3 * i + j] = b->R[3 * j + i];
+    mat3_mul(b->R, b->Ib, tmp);
+    mat3_mul(tmp, Rt, Iw);
+    double wd[3];
+    if (solve3(Iw, Mt, wd)) { set_err("singular inertia"); return ORC_EUNSTABLE; }
+    double un[3], wn[3];
+    for (int a = 0; a < 3; ++a) {
+        un[a] = 2.0 / 3.0 * (2.0 * b->ur[a] - 0.5 * b->ur1[a] + F[a] / b->mass);
+        wn[a] = 2.0 / 3.0 * (2.0 * b->om[a] - 0.5 * b->om1[a] + wd[a]);
+    }
+    memcpy(b->ur1, b->ur, sizeof un); memcpy(b->ur, un, sizeof un);
+    memcpy(b->om1, b->om, sizeof wn); memcpy(b->om, wn, sizeof wn);
+    for (int a = 0; a < 3; ++a) b->X[a] += un[a];
+    double Rw[9], Rn[9];
+    rotation_from_vector(wn, Rw);
+    mat3_mul(Rw, b->R, Rn);
+    memcpy(b->R, Rn, sizeof Rn);
+    memcpy(b->xprev, b->x, sizeof(double) * 3 * b->nv);
+    for (int v = 0; v < b->nv; ++v)
+        for (int a = 0; a < 3; ++a) {
+            double s = b->X[a];
+            for (int c = 0; c < 3; ++c) s += b->R[3 * a + c] * b->xb[3 * v + c];
+            b->x[3 * v + a] = s;
+        }
+    for (int i = 0; i < 3 * b->nv; ++i)
+        if (!isfinite(b->x[i])) { set_err("non-finite body state"); return ORC_EUNSTABLE; }
+    return ORC_OK;
+}
+
+int orc_rigid_advance(orc_lattice* L, int32_t id, const double F[3], const double M[3]) {
+    if (id < 0 || id >= L->nb || !L->b[id]->d.rigid) { set_err("no such rigid body"); return ORC_EINVAL; }
+    body_t* b = L->b[id];
+    memcpy(b->Ftot, F, sizeof(double) * 3);
+    memcpy(b->Mtot, M, sizeof(double) * 3);
+    return rigid_advance(b, F, M);
+}
+
+int orc_body_rigid_state(const orc_lattice* L, int32_t id, double X[3], double R[9], double u[3],
+                         double om[3]) {
+    if (id < 0 || id >= L->nb || !L->b[id]->d.rigid) { set_err("no such rigid body"); return ORC_EINVAL; }
+    const body_t* b = L->b[id];
+    memcpy(X, b->X, sizeof(double) * 3);
+    memcpy(R, b->R, sizeof(double) * 9);
+    memcpy(u, b->ur, sizeof(double) * 3);
+    memcpy(om, b->om, sizeof(double) * 3);
+    return ORC_OK;
+}
+
 static int structure_update(orc_lattice* L, body_t* b) {
     const long N = L->N;
     double* Fext = (double*)malloc(sizeof(double) * 3 * b->nt);
@@ -1266,40 +1338,7 @@ static int structure_update(orc_lattice* L, body_t* b) {
         for (int j = 0; j < 3; ++j)
             for (int a = 0; a < 3; ++a) b->Fv[3 * b->tri[3 * t + j] + a] += Fext[3 * t + a] / 3.0;
     free(Fext);
-    if (b->d.rigid) {
-        /* Eqs. linearVelRig / angularVelRig with udot = F/m, omegadot = I^-1 M */
-        double F[3];
-        for (int a = 0; a < 3; ++a) F[a] = Ft[a] + (b->mass - b->V0) * b->d.gravity[a];
-        double Iw[9], tmp[9], Rt[9];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) Rt[3 * i + j] = b->R[3 * j + i];
-        mat3_mul(b->R, b->Ib, tmp);
-        mat3_mul(tmp, Rt, Iw);
-        double wd[3];
-        if (solve3(Iw, Mt, wd)) { set_err("singular inertia"); return ORC_EUNSTABLE; }
-        double un[3], wn[3];
-        for (int a = 0; a < 3; ++a) {
-            un[a] = 2.0 / 3.0 * (2.0 * b->ur[a] - 0.5 * b->ur1[a] + F[a] / b->mass);
-            wn[a] = 2.0 / 3.0 * (2.0 * b->om[a] - 0.5 * b->om1[a] + wd[a]);
-        }
-        memcpy(b->ur1, b->ur, sizeof un); memcpy(b->ur, un, sizeof un);
-        memcpy(b->om1, b->om, sizeof wn); memcpy(b->om, wn, sizeof wn);
-        for (int a = 0; a < 3; ++a) b->X[a] += un[a];
-        double Rw[9], Rn[9];
-        rotation_from_vector(wn, Rw);
-        mat3_mul(Rw, b->R, Rn);
-        memcpy(b->R, Rn, sizeof Rn);
-        memcpy(b->xprev, b->x, sizeof(double) * 3 * b->nv);
-        for (int v = 0; v < b->nv; ++v)
-            for (int a = 0; a < 3; ++a) {
-                double s = b->X[a];
-                for (int c = 0; c < 3; ++c) s += b->R[3 * a + c] * b->xb[3 * v + c];
-                b->x[3 * v + a] = s;
-            }
-        for (int i = 0; i < 3 * b->nv; ++i)
-            if (!isfinite(b->x[i])) { set_err("non-finite body state"); return ORC_EUNSTABLE; }
-        return ORC_OK;
-    }
+    if (b->d.rigid) return rigid_advance(b, Ft, Mt);
     /* membrane: Eq. (newtonSoft) with internal forces at x^n, Verlet Eqs. verletPos/verletVel */
     double* Fi = (double*)malloc(sizeof(double) * 3 * b->nv);
     membrane_forces(b, b->x, Fi, NULL);

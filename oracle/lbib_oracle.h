@@ -77,6 +77,8 @@ int64_t orc_step_count(const orc_lattice* L);
 int orc_body_add(orc_lattice* L, const orc_body_desc* d, const double* xyz, int32_t nv,
                  const int32_t* tri, int32_t nt, int32_t* body_id);
 int orc_body_set_velocity(orc_lattice* L, int32_t b, const double* v);
+/* Membranes: place the body at rest at xyz (x^n = x^{n-1} = xyz, u_v = 0). */
+int orc_body_set_positions(orc_lattice* L, int32_t b, const double* xyz);
 int orc_body_get_state(const orc_lattice* L, int32_t b, double* xyz, double* vel);
 int orc_body_get_forces(const orc_lattice* L, int32_t b, double* f_vertex, double F[3], double M[3]);
 int orc_body_counts(const orc_lattice* L, int32_t b, int32_t* nv, int32_t* nt, int32_t* ne);
@@ -84,6 +86,9 @@ int orc_body_topology(const orc_lattice* L, int32_t b, int32_t* edge, int32_t* h
 int orc_body_rest(const orc_lattice* L, int32_t b, double* l0, double* ks, double* theta0,
                   double* A0, double scal[4] /* V0, S0, m_v, rigid mass */);
 int orc_body_rigid_props(const orc_lattice* L, int32_t b, double X0[3], double* mass, double I[9]);
+/* Rigid pose and velocities: centre X, rotation R (row-major, x = X + R x_body), u, omega. */
+int orc_body_rigid_state(const orc_lattice* L, int32_t b, double X[3], double R[9], double u[3],
+                         double om[3]);
 
 /* --- pieces of one step, evaluated on the current state without advancing it --- */
 int orc_membrane_forces(const orc_lattice* L, int32_t b, const double* xyz, double* F, double E[3]);
@@ -91,6 +96,9 @@ int orc_mls(const orc_lattice* L, const double x[3], double rw, double alpha, in
             double d[81], double phi[27], double grad[81], int32_t* count);
 int orc_ib_force(orc_lattice* L, double* flb, double* U, double* Fl);
 int orc_body_probe_forces(const orc_lattice* L, int32_t b, double* Fext);
+/* The rigid-body part of the structure update (Eqs. linearVelRig, angularVelRig and the pose)
+ * with given hydrodynamic totals F, M in place of the probe totals; the fluid is untouched. */
+int orc_rigid_advance(orc_lattice* L, int32_t b, const double F[3], const double M[3]);
 
 #ifdef __cplusplus
 }
