@@ -70,7 +70,10 @@ typedef enum { LBIB_BC_PERIODIC = 0, LBIB_BC_ZOUHE_VELOCITY = 1, LBIB_BC_BOUNCEB
 /* Population storage.  All forms store the deviation g_i = f_i - w_i from the lattice
  * weights and collide in FP32; FP16/BF16 narrow with round-to-nearest-even and keep
  * subnormals.  FP16 holds g_i * 2^12 (an exact power-of-two scale that keeps small deviations
- * in the normal range); BF16 holds g_i. */
+ * in the normal range) and is the reduced-precision form: it stays within 1e-3 (relative L2 of
+ * the velocity) of the FP64 scheme.  BF16 holds g_i; its 8 significand bits do NOT meet that
+ * bound (about 2e-2 on a sheared box after 300 steps) and it is kept for bandwidth studies
+ * only. */
 typedef enum { LBIB_STORE_F32 = 0, LBIB_STORE_F16 = 1, LBIB_STORE_BF16 = 2 } lbib_storage;
 
 /* Membrane vertex update.  DISPLACEMENT: position by Eq. (verletPos) with the interpolated
@@ -100,9 +103,9 @@ typedef struct {
     double kv;                /* volume penalty constant k_v (Eq. volFor) */
     double mass_ratio;        /* solid/fluid density ratio; > 0 */
     double gravity[3];        /* rigid bodies only: net weight (m - rho_f V) g */
-    double mls_rw;            /* MLS support radius r_w (1.3 in Sec. 1.2) */
+    double mls_rw;            /* MLS support radius r_w (1.3 in Sec. 1.2); below 1.5 */
     double mls_alpha;         /* MLS weight width alpha (0.3 in Eq. intKernel) */
-    double probe_len;         /* probe distance (1.2 in Sec. 1.3) */
+    double probe_len;         /* probe distance (1.2 in Sec. 1.3); at most 2.5 */
     double shell_h;           /* marker thickness h in c_l = A_l h / dx^3 */
 } lbib_body_desc;
 
@@ -116,7 +119,12 @@ const char* lbib_last_error(void);
 /* ---------------------------------------------------------------- single lattice */
 
 /* Device bytes needed by one lattice of this descriptor plus one body of up to max_nv
- * vertices / max_nt triangles (0, 0 for no body).  Errors: EINVAL for a bad descriptor. */
+ * vertices / max_nt triangles (0, 0 for no body) whose vertices have at most 12 incident
+ * triangles each: the exact size of the buffers lbib_lattice_create and lbib_body_add carve
+ * from a workspace, with the force window sized for the whole lattice.  A lattice created in
+ * such a workspace calls no hipMalloc afterwards: setters and getters stage their transfers in
+ * the population buffer that the next step overwrites.  Errors: EINVAL for a bad descriptor or
+ * mesh size. */
 lbib_status lbib_workspace_bytes(const lbib_lattice_desc* desc, int32_t max_nv, int32_t max_nt,
                                  size_t* bytes);
 

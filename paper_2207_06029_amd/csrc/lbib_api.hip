@@ -135,13 +135,8 @@ lbib_status lbib_workspace_bytes(const lbib_lattice_desc* desc, int32_t max_nv, 
     if (!desc || !bytes) return fail(LBIB_EINVAL, "null argument");
     lbib_status st = lbib::check_lattice(*desc);
     if (st) return st;
-    const size_t n = (size_t)desc->nx * desc->ny * desc->nz;
-    size_t b = 2 * 19 * n * lbib::storage_bytes(desc->storage) + 4096;
-    if (max_nv > 0) {
-        // mesh state and topology, plus force and moment windows no larger than the lattice
-        b += (size_t)max_nv * 8 * 32 + (size_t)max_nt * 8 * 16 + n * (24 + 16) + (1 << 20);
-    }
-    *bytes = b;
+    if (max_nv < 0 || max_nt < 0 || (max_nv > 0) != (max_nt > 0)) return fail(LBIB_EINVAL, "bad mesh size");
+    *bytes = lbib::workspace_need(*desc, max_nv, max_nt);
     return LBIB_OK;
 }
 

@@ -200,6 +200,8 @@ struct SweepShape {
 // Chunked XCD order pays while the two population buffers stay in the Infinity Cache (256 MB);
 // beyond it, dispatch order keeps all XCDs streaming the same region.
 constexpr int XCD_CHUNK = 8;
+// nodes of the smallest sweep tile (block size x nodes per thread) of any launch shape
+constexpr int MIN_TILE_NODES = 128;
 constexpr long long XCD_CHUNK_MAX_BYTES = 192LL << 20;
 
 // lbib_lattice.hip
@@ -215,12 +217,15 @@ void launch_macros(const Pools& P, int storage, bool from_b, int job, long long 
 // rho[n] then u*[3n] in double (the host layout of lbib_get_macros), written to out[4n]
 void launch_macros_f64(const Pools& P, int storage, bool from_b, int job, long long n, double* out,
                        hipStream_t s);
-void launch_get_pops(const Pools& P, int storage, bool from_b, int job, long long n, float* out,
-                     hipStream_t s);
-void launch_set_pops(const Pools& P, int storage, bool to_b, int job, long long n,
-                     const double* f, hipStream_t s);
-void launch_init_eq(int job, long long n, const double* rho, const double* u, double* f_out,
-                    hipStream_t s);
+// Population `plane` of the post-streaming state, widened to double, into out[n].
+void launch_get_pop_plane(const Pools& P, int storage, bool from_b, int job, long long n, int plane,
+                          double* out, hipStream_t s);
+// Set population `plane` of the post-streaming state from f[n] (double).
+void launch_set_pop_plane(const Pools& P, int storage, bool to_b, int job, long long n, int plane,
+                          const double* f, hipStream_t s);
+// Equilibrium of rho[n], u[3n] (device; NULL: 1 and 0) as the post-streaming state.
+void launch_init_eq(const Pools& P, int storage, bool to_b, int job, long long n, const double* rho,
+                    const double* u, hipStream_t s);
 
 // lbib_ib.hip
 // fold: the centroid blocks derive this step's force window from the vertex-block boxes

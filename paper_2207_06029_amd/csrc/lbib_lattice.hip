@@ -538,8 +538,10 @@ __global__ void k_macros_f64(Pools P, int from_b, int job, double* out) {
     out[3 * J.n + k] = (double)m.w;
 }
 
+// Population i of node k, post-streaming, widened to double: f_i = w_i + g_i.  The full pull
+// runs for every i (the wall closure needs all of them); only plane i is written.
 template <typename S>
-__global__ void k_get_pops(Pools P, int from_b, int job, float* out) {
+__global__ void k_get_pop_plane(Pools P, int from_b, int job, int plane, double* out) {
     const JobDev& J = P.jobs[job];
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= J.n) return;
@@ -548,69 +550,84 @@ __global__ void k_get_pops(Pools P, int from_b, int job, float* out) {
     const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
     float g[Q];
     pull<S>(src, J, x, y, z, k, g);
+    float gi = g[0];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) out[(long long)i * J.n + k] = g[i];
+    for (int i = 1; i < Q; ++i)
+        if (i == plane) gi = g[i];
+    out[k] = wq(plane) + (double)gi;
 }
 
-// Inverse of the pull: write the post-collision entries whose pull reproduces f.  Entries
-// pulled from behind a Zou-He face are not representable; the closure rebuilds them, on edges
-// and corners from a density that the given unknown values, stored in the redirected slots,
-// make equal to the given one.
+// Inverse of the pull for population i of node (x, y, z): write the post-collision entry whose
+// pull reproduces f_i.  Entries pulled from behind a Zou-He face are not representable; the
+// closure rebuilds them, on edges and corners from a density that the given unknown values,
+// stored in the redirected slots, make equal to the given one.  Every destination entry is
+// written by exactly one (node, i), so the populations can be set one plane at a time.
 template <typename S>
-__global__ void k_set_pops(Pools P, int to_b, int job, const double* f) {
+__device__ __forceinline__ void set_one(const JobDev& J, S* __restrict__ dst, int x, int y, int z,
+                                        long long k, int i, double fi) {
+    const float gi = (float)(fi - wq(i));
+    const int n[3] = {J.nx, J.ny, J.nz};
+    const int c[3] = {x, y, z};
+    int s[3];
+    int face = -1, nout = 0;
+    float uw[3] = {0.f, 0.f, 0.f};
+    bool zh = false;
+    for (int a = 0; a < 3; ++a) {
+        s[a] = c[a] - ce(i, a);
+        if (s[a] < 0 || s[a] >= n[a]) {
+            const int fa = 2 * a + (s[a] < 0 ? 0 : 1);
+            if (J.bc[fa] == 0) {
+                s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
+            } else {
+                ++nout;
+                if (face < 0) face = fa;
+                if (J.bc[fa] == 1) zh = true;
+                uw[0] += J.wall_u[fa][0]; uw[1] += J.wall_u[fa][1]; uw[2] += J.wall_u[fa][2];
+            }
+        }
+    }
+    if (nout == 0) {
+        Codec<S>::st(dst + (long long)i * J.n + s[0] + (long long)n[0] * (s[1] + (long long)n[1] * s[2]), gi);
+    } else if (!zh && J.bc[face] == 2) {
+        const float eu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
+        Codec<S>::st(dst + (long long)opp(i) * J.n + k, gi - (float)(6.0 * wq(i)) * eu);
+    } else if (zh) {
+        // the redirected slot: the edge and corner closure reads it as the mass the node sent
+        // out through its walls, so the given density is kept
+        Codec<S>::st(dst + (long long)opp(i) * J.n + k, gi);
+    }
+}
+
+// Population `plane` of every node from f_plane[N] (double).
+template <typename S>
+__global__ void k_set_pop_plane(Pools P, int to_b, int job, int plane, const double* f) {
     const JobDev& J = P.jobs[job];
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= J.n) return;
     int x, y, z;
     node_coords(J, k, x, y, z);
     S* dst = (S*)(to_b ? P.popB : P.popA) + J.pop_off;
-    const int n[3] = {J.nx, J.ny, J.nz};
-    const int c[3] = {x, y, z};
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const float gi = (float)(f[(long long)i * J.n + k] - wq(i));
-        int s[3];
-        int face = -1, nout = 0;
-        float uw[3] = {0.f, 0.f, 0.f};
-        bool zh = false;
-        for (int a = 0; a < 3; ++a) {
-            s[a] = c[a] - ce(i, a);
-            if (s[a] < 0 || s[a] >= n[a]) {
-                const int fa = 2 * a + (s[a] < 0 ? 0 : 1);
-                if (J.bc[fa] == 0) {
-                    s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
-                } else {
-                    ++nout;
-                    if (face < 0) face = fa;
-                    if (J.bc[fa] == 1) zh = true;
-                    uw[0] += J.wall_u[fa][0]; uw[1] += J.wall_u[fa][1]; uw[2] += J.wall_u[fa][2];
-                }
-            }
-        }
-        if (nout == 0) {
-            Codec<S>::st(dst + (long long)i * J.n + s[0] + (long long)n[0] * (s[1] + (long long)n[1] * s[2]), gi);
-        } else if (!zh && J.bc[face] == 2) {
-            const float eu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
-            Codec<S>::st(dst + (long long)opp(i) * J.n + k, gi - (float)(6.0 * wq(i)) * eu);
-        } else if (zh) {
-            // the redirected slot: the edge and corner closure reads it as the mass the node
-            // sent out through its walls, so the given density is kept
-            Codec<S>::st(dst + (long long)opp(i) * J.n + k, gi);
-        }
-    }
+    set_one<S>(J, dst, x, y, z, k, plane, f[k]);
 }
 
-// Equilibrium Eq. (eqfunc) of given rho, u, in double, as post-streaming populations.
-__global__ void k_init_eq(long long n, const double* rho, const double* u, double* f) {
+// Equilibrium Eq. (eqfunc) of rho[N], u[3N] (NULL: 1 and 0), in double, set as the
+// post-streaming populations of every node.
+template <typename S>
+__global__ void k_init_eq(Pools P, int to_b, int job, const double* rho, const double* u) {
+    const JobDev& J = P.jobs[job];
+    const long long n = J.n;
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
+    int x, y, z;
+    node_coords(J, k, x, y, z);
+    S* dst = (S*)(to_b ? P.popB : P.popA) + J.pop_off;
     const double r = rho ? rho[k] : 1.0;
     const double ux = u ? u[k] : 0.0, uy = u ? u[n + k] : 0.0, uz = u ? u[2 * n + k] : 0.0;
     const double uu = ux * ux + uy * uy + uz * uz;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double eu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-        f[(long long)i * n + k] = wq(i) * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        set_one<S>(J, dst, x, y, z, k, i, wq(i) * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
     }
 }
 
@@ -631,19 +648,20 @@ void launch_macros_f64(const Pools& P, int storage, bool from_b, int job, long l
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     LBIB_DISPATCH(storage, k_macros_f64, grid, block, s, P, (int)from_b, job, out);
 }
-void launch_get_pops(const Pools& P, int storage, bool from_b, int job, long long n, float* out,
-                     hipStream_t s) {
+void launch_get_pop_plane(const Pools& P, int storage, bool from_b, int job, long long n, int plane,
+                          double* out, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    LBIB_DISPATCH(storage, k_get_pops, grid, block, s, P, (int)from_b, job, out);
+    LBIB_DISPATCH(storage, k_get_pop_plane, grid, block, s, P, (int)from_b, job, plane, out);
 }
-void launch_set_pops(const Pools& P, int storage, bool to_b, int job, long long n,
-                     const double* f, hipStream_t s) {
+void launch_set_pop_plane(const Pools& P, int storage, bool to_b, int job, long long n, int plane,
+                          const double* f, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    LBIB_DISPATCH(storage, k_set_pops, grid, block, s, P, (int)to_b, job, f);
+    LBIB_DISPATCH(storage, k_set_pop_plane, grid, block, s, P, (int)to_b, job, plane, f);
 }
-void launch_init_eq(int, long long n, const double* rho, const double* u, double* f, hipStream_t s) {
+void launch_init_eq(const Pools& P, int storage, bool to_b, int job, long long n, const double* rho,
+                    const double* u, hipStream_t s) {
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    hipLaunchKernelGGL(k_init_eq, grid, block, 0, s, n, rho, u, f);
+    LBIB_DISPATCH(storage, k_init_eq, grid, block, s, P, (int)to_b, job, rho, u);
 }
 
 }  // namespace lbib

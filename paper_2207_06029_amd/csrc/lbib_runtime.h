@@ -17,6 +17,9 @@ lbib_status fail_static(lbib_status code, const char* msg);
 const char* last_error();
 lbib_status check_lattice(const lbib_lattice_desc& d);
 size_t storage_bytes(int storage);
+// vertex valence (incident triangles) the workspace estimate budgets for
+constexpr int WS_MAX_VALENCE = 12;
+size_t workspace_need(const lbib_lattice_desc& d, long long nv, long long nt);
 // Force-window capacity per axis for a body of bounding radius rbound about its vertex mean.
 void window_capacity(const int dims[3], bool rigid, double rbound, int cap[3]);
 
@@ -58,8 +61,9 @@ struct Batch {
     std::vector<lbib_lattice_desc> ldesc;
     std::vector<JobDev> jobs;
     std::vector<int> tile_job;
-    int* d_tile_job = nullptr;
+    int* d_tile_job = nullptr;     // from the arena, tile_cap entries
     size_t tile_cap = 0;
+    double* d_totals = nullptr;    // 6 doubles: membrane force/torque totals on their way out
     JobDev* d_jobs = nullptr;
     BodyDev* d_bodies = nullptr;
     long long pop_elems = 0;
@@ -99,6 +103,7 @@ struct Batch {
     lbib_status add_body(int job, const lbib_body_desc& d, const double* xyz, int nv,
                          const int* tri, int nt, int* id);
     int body_index(int job, int local) const;
+    void* spare(int job) const;
     lbib_status init_job(int job, const double* rho, const double* u);
     lbib_status set_populations(int job, const double* f);
     lbib_status get_macros(int job, double* rho, double* u);

@@ -33,19 +33,6 @@ const char* last_error() { return g_err_static ? g_err_static : g_err.c_str(); }
         if (e_ != hipSuccess) return fail(LBIB_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-// Temporary device buffer of one host call, released on every return path.
-template <typename T>
-struct DevTemp {
-    T* p = nullptr;
-    hipError_t alloc(size_t count) { return hipMalloc(&p, sizeof(T) * (count > 0 ? count : 1)); }
-    DevTemp() = default;
-    DevTemp(const DevTemp&) = delete;
-    DevTemp& operator=(const DevTemp&) = delete;
-    ~DevTemp() {
-        if (p) (void)hipFree(p);
-    }
-};
-
 // ---------------------------------------------------------------- device allocation
 lbib_status Arena::alloc(size_t bytes, void** out) {
     bytes = (bytes + 255) & ~size_t(255);
@@ -128,6 +115,35 @@ lbib_status check_lattice(const lbib_lattice_desc& d) {
     return LBIB_OK;
 }
 
+// Device bytes of one lattice of descriptor d with one body of nv vertices and nt triangles
+// (nv = 0: no body), as create_lattices and rebuild_bodies carve them from a workspace: every
+// allocation rounded up to 256 bytes, at least one element each.  A closed triangle mesh has
+// ne = 3 nt / 2 edges; the padded incidence lists are budgeted for vertices with up to
+// WS_MAX_VALENCE incident triangles, the force and moment windows for a capacity of the whole
+// lattice (their upper bound).
+size_t workspace_need(const lbib_lattice_desc& d, long long nv, long long nt) {
+    auto r = [](long long bytes) -> size_t { return (size_t)((std::max<long long>(bytes, 1) + 255) & ~255LL); };
+    const long long n = (long long)d.nx * d.ny * d.nz;
+    size_t b = 2 * r(19 * n * (long long)storage_bytes(d.storage)) + r(sizeof(int)) + r(sizeof(JobDev)) +
+               r(sizeof(int) * ((n + MIN_TILE_NODES - 1) / MIN_TILE_NODES));
+    const bool body = nv > 0;
+    if (!body) nv = nt = 0;
+    const long long ne = 3 * nt / 2;
+    const long long nbc = (nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbt = (nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
+    const long long nbv = (nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbe = (ne + 255) / 256;
+    const long long capn = body ? n : 0;
+    const long long nbw = body ? std::max<long long>(1, (capn + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK) : 0;
+    b += r(sizeof(BodyDev)) + r(4 * nbc) + r(4 * nbe) + r(4 * nbt) + r(4 * nbv) + r(4 * nbw);
+    b += 6 * r(24 * nv);                                             // x, xprev, uv, fv, u0v, xb
+    b += r(12 * nt) + r(8 * ne) + r(16 * ne) + 3 * r(8 * ne);        // tri, edge, hinge, l0, ks, theta0
+    b += r(4 * nv * WS_MAX_VALENCE) + r(4 * nv * 2 * WS_MAX_VALENCE);  // incidence lists
+    b += 2 * r(24 * std::max<long long>(nt, 1)) + r(48 * std::max<long long>(nt, 1));  // fext, fvol, tgeo
+    b += r(120 * std::max<long long>(ne, 1));                        // fedge
+    b += r(24 * std::max<long long>(capn, 1)) + r(16 * std::max<long long>(capn, 1));  // fwin, mwin
+    b += 2 * r(sizeof(WinDesc)) + r(sizeof(BodyState)) + r(128 * std::max(nbc, nbt)) + r(24 * nbv) + r(48);
+    return b;
+}
+
 void window_capacity(const int dims[3], bool rigid, double rbound, int cap[3]) {
     // membranes may stretch to 2.5 times their rest extent (a Taylor deformation near 0.6 at
     // fixed volume) before the window overflows; rigid bodies only carry their box along.  Only
@@ -167,6 +183,13 @@ lbib_status build_body(const lbib_body_desc& d, const double* xyz, int nv, const
     if (nv < 4 || nt < 4) return fail(LBIB_EINVAL, "mesh too small");
     if (!(d.mls_rw > 0) || !(d.mls_alpha > 0) || !(d.probe_len >= 0) || !(d.shell_h > 0))
         return fail(LBIB_EINVAL, "bad MLS / probe / shell parameters");
+    // the kernels evaluate the 3x3x3 block around the nearest node, which holds every node
+    // within r_w of the point only for r_w < 1.5
+    if (!(d.mls_rw < 1.5)) return fail(LBIB_EINVAL, "mls_rw must be below 1.5 (the MLS support is the 3x3x3 block around the nearest node)");
+    // a probe's block reaches probe_len + 1.5 beyond the vertex bounding box, which the force and
+    // moment windows extend by WIN_MARGIN
+    if (!(d.probe_len + 1.5 <= WIN_MARGIN))
+        return fail(LBIB_EINVAL, "probe_len must be at most " + std::to_string(WIN_MARGIN - 1.5) + " (window margin)");
     if (!(d.mass_ratio > 0)) return fail(LBIB_EINVAL, "mass ratio must be positive");
     if (d.integrator < 0 || d.integrator > 2) return fail(LBIB_EINVAL, "unknown integrator");
     if (!d.rigid && (d.gravity[0] != 0 || d.gravity[1] != 0 || d.gravity[2] != 0))
@@ -397,6 +420,11 @@ lbib_status Batch::create_lattices(const std::vector<lbib_lattice_desc>& descs, 
     if ((st = arena.alloc(sizeof(JobDev) * jobs.size(), &p))) return st;
     d_jobs = (JobDev*)p;
     P.jobs = d_jobs;
+    // sweep tile table, sized for the smallest tile any launch shape uses
+    tile_cap = 0;
+    for (auto& J : jobs) tile_cap += (size_t)((J.n + MIN_TILE_NODES - 1) / MIN_TILE_NODES);
+    if ((st = arena.alloc(sizeof(int) * std::max<size_t>(tile_cap, 1), &p))) return st;
+    d_tile_job = (int*)p;
     mark_used = arena.used;
     mark_owned = arena.owned.size();
     if ((st = retile())) return st;
@@ -419,16 +447,9 @@ lbib_status Batch::retile() {
         pop_bytes += 2LL * Q * (long long)storage_bytes(storage) * jobs[j].n;
     }
     xcd_chunk = shape.xcd_chunk >= 0 ? shape.xcd_chunk : (pop_bytes <= XCD_CHUNK_MAX_BYTES ? XCD_CHUNK : 0);
+    if (tile_job.size() > tile_cap)
+        return fail(LBIB_EINVAL, "sweep launch shape below " + std::to_string(MIN_TILE_NODES) + " nodes per tile");
     HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, stream));
-    if (d_tile_job && tile_cap < tile_job.size()) {
-        HIP_TRY(hipStreamSynchronize(stream));
-        HIP_TRY(hipFree(d_tile_job));
-        d_tile_job = nullptr;
-    }
-    if (!d_tile_job) {
-        tile_cap = std::max<size_t>(tile_job.size(), 1) * 4;
-        HIP_TRY(hipMalloc(&d_tile_job, sizeof(int) * tile_cap));
-    }
     HIP_TRY(hipMemcpyAsync(d_tile_job, tile_job.data(), sizeof(int) * tile_job.size(), hipMemcpyHostToDevice, stream));
     P.tile_job = d_tile_job;
     graph_valid = false;
@@ -599,6 +620,8 @@ lbib_status Batch::rebuild_bodies() {
     if ((st = arena.alloc(sizeof(double) * 16 * std::max<long long>(red, 1), &p))) return st;
     P.partial = (double*)p;
     if ((st = upload(arena, vbox, &P.vbox, stream))) return st;
+    if ((st = arena.alloc(sizeof(double) * 6, &p))) return st;
+    d_totals = (double*)p;
     d_bodies = (BodyDev*)P.bodies;
     host_bodies = bd;
     HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, stream));
@@ -659,20 +682,21 @@ int Batch::body_index(int job, int local) const {
 }
 
 // ---------------------------------------------------------------- state
+// The population buffer that does not hold the current state: its region of a job is dead
+// until the next sweep overwrites it, so host transfers stage through it (19 n s bytes per
+// job: at least 38 bytes per node) and no call needs device memory of its own.
+void* Batch::spare(int job) const {
+    return (char*)(cur_b ? P.popA : P.popB) + jobs[job].pop_off * storage_bytes(storage);
+}
+
 lbib_status Batch::init_job(int job, const double* rho, const double* u) {
     const long long n = jobs[job].n;
-    DevTemp<double> drho, du, df;
-    if (rho) {
-        HIP_TRY(drho.alloc(n));
-        HIP_TRY(hipMemcpyAsync(drho.p, rho, sizeof(double) * n, hipMemcpyHostToDevice, stream));
-    }
-    if (u) {
-        HIP_TRY(du.alloc(3 * n));
-        HIP_TRY(hipMemcpyAsync(du.p, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, stream));
-    }
-    HIP_TRY(df.alloc(19 * n));
-    launch_init_eq(job, n, drho.p, du.p, df.p, stream);
-    launch_set_pops(P, storage, cur_b, job, n, df.p, stream);
+    // rho (8 n bytes) and u (24 n bytes) staged in the spare buffer
+    double* drho = rho ? (double*)spare(job) : nullptr;
+    double* du = u ? (double*)spare(job) + n : nullptr;
+    if (rho) HIP_TRY(hipMemcpyAsync(drho, rho, sizeof(double) * n, hipMemcpyHostToDevice, stream));
+    if (u) HIP_TRY(hipMemcpyAsync(du, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, stream));
+    launch_init_eq(P, storage, cur_b, job, n, drho, du, stream);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(stream));
     primed = false;
@@ -682,11 +706,12 @@ lbib_status Batch::init_job(int job, const double* rho, const double* u) {
 
 lbib_status Batch::set_populations(int job, const double* f) {
     const long long n = jobs[job].n;
-    DevTemp<double> df;
-    HIP_TRY(df.alloc(19 * n));
-    HIP_TRY(hipMemcpyAsync(df.p, f, sizeof(double) * 19 * n, hipMemcpyHostToDevice, stream));
-    launch_set_pops(P, storage, cur_b, job, n, df.p, stream);
-    HIP_TRY(hipGetLastError());
+    double* plane = (double*)spare(job);
+    for (int i = 0; i < Q; ++i) {
+        HIP_TRY(hipMemcpyAsync(plane, f + (size_t)i * n, sizeof(double) * n, hipMemcpyHostToDevice, stream));
+        launch_set_pop_plane(P, storage, cur_b, job, n, i, plane, stream);
+        HIP_TRY(hipGetLastError());
+    }
     HIP_TRY(hipStreamSynchronize(stream));
     primed = false;
     return LBIB_OK;
@@ -713,12 +738,11 @@ lbib_status Batch::job_flags(std::vector<int>& fl) {
 
 lbib_status Batch::get_macros(int job, double* rho, double* u) {
     const long long n = jobs[job].n;
-    DevTemp<float> d;
-    HIP_TRY(d.alloc(4 * n));
-    launch_macros(P, storage, cur_b, job, n, d.p, stream);
+    float* d = (float*)spare(job);   // 16 n bytes
+    launch_macros(P, storage, cur_b, job, n, d, stream);
     HIP_TRY(hipGetLastError());
     std::vector<float> h(4 * n);
-    HIP_TRY(hipMemcpyAsync(h.data(), d.p, sizeof(float) * 4 * n, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(h.data(), d, sizeof(float) * 4 * n, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     for (long long k = 0; k < n; ++k) {
         if (rho) rho[k] = 1.0 + (double)h[4 * k];
@@ -729,15 +753,13 @@ lbib_status Batch::get_macros(int job, double* rho, double* u) {
 
 lbib_status Batch::get_populations(int job, double* f) {
     const long long n = jobs[job].n;
-    DevTemp<float> d;
-    HIP_TRY(d.alloc(19 * n));
-    launch_get_pops(P, storage, cur_b, job, n, d.p, stream);
-    HIP_TRY(hipGetLastError());
-    std::vector<float> h(19 * n);
-    HIP_TRY(hipMemcpyAsync(h.data(), d.p, sizeof(float) * 19 * n, hipMemcpyDeviceToHost, stream));
+    double* plane = (double*)spare(job);
+    for (int i = 0; i < Q; ++i) {
+        launch_get_pop_plane(P, storage, cur_b, job, n, i, plane, stream);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(f + (size_t)i * n, plane, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+    }
     HIP_TRY(hipStreamSynchronize(stream));
-    for (int i = 0; i < 19; ++i)
-        for (long long k = 0; k < n; ++k) f[i * n + k] = wq(i) + (double)h[i * n + k];
     return LBIB_OK;
 }
 
@@ -880,7 +902,6 @@ Batch::~Batch() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
-    if (d_tile_job) (void)hipFree(d_tile_job);
 }
 
 // ---------------------------------------------------------------- body state access
@@ -903,11 +924,9 @@ lbib_status Batch::body_forces(int bi, double* fv, double* F, double* M) {
         for (int a = 0; a < 3; ++a) { tot[a] = S.F[a]; tot[3 + a] = S.M[a]; }
     } else {
         // membranes: totals of the last step's probe forces, reduced on the device in FP64
-        DevTemp<double> d;
-        HIP_TRY(d.alloc(6));
-        launch_body_totals(P, bi, d.p, stream);
+        launch_body_totals(P, bi, d_totals, stream);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(tot, d.p, sizeof tot, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(tot, d_totals, sizeof tot, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
     }
     if (F) for (int a = 0; a < 3; ++a) F[a] = tot[a];

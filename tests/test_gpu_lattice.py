@@ -116,15 +116,23 @@ def test_moving_bounceback_box_parity(api, orc):
     assert np.abs(rho - rr).max() < 1e-7
 
 
-# FP16 deviations meet the 1e-3 reduced-precision gate; BF16 (8 significand bits) does not: it
-# measures ~2e-2 here, and the bound below only documents that level.
-@pytest.mark.parametrize("storage,tol", [(I.STORE_F16, 1e-3), (I.STORE_BF16, 5e-2)])
-def test_reduced_precision_storage(api, orc, storage, tol):
+def _reduced_precision_error(api, orc, storage):
     spec = I.LatticeSpec(16, 17, 8, 0.8, storage=storage, **I.shear_walls(0.02))
     (rho, u), (rr, ur), *_ = _fluid_case(spec, 7, 300, orc, api)
     err = rel_l2(u, ur)
     print(f"storage {storage}: rel-L2 u* after 300 steps {err:.3e}")
-    assert err < tol
+    return err
+
+
+def test_reduced_precision_storage_fp16(api, orc):
+    """FP16 shifted deviations meet the 1e-3 reduced-precision gate."""
+    assert _reduced_precision_error(api, orc, I.STORE_F16) < 1e-3
+
+
+@pytest.mark.xfail(strict=True, reason="BF16 storage does not meet the 1e-3 reduced-precision gate: "
+                   "its 8 significand bits give about 2e-2 on this case")
+def test_reduced_precision_storage_bf16_gate(api, orc):
+    assert _reduced_precision_error(api, orc, I.STORE_BF16) < 1e-3
 
 
 def test_errors_surface(api):

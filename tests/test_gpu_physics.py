@@ -74,4 +74,4 @@ def test_jeffery_orbit_rigid_prolate(api):
     period = (t2 - t1) * gamma
     print(f"Jeffery half period T*gamma = {period:.4f} (closed form {math.pi * 2.5:.4f}), "
           f"gamma {gamma:.3e}, Re {re}, {total} steps")
-    assert abs(period - math.pi * 2.5) / (math.pi * 2.5) < 0.05
+    assert abs(period - math.pi * 2.5) / (math.pi * 2.5) < 0.01
