@@ -118,6 +118,13 @@ def load(path: str = SO):
         if not os.path.exists(path):
             raise ImportError(f"{path} is missing: build it with paper_2207_06029_amd.build "
                               "(or __graft_entry__.build())")
+        # torch (device memory and streams for callers) ships its own HIP runtime: load it first
+        # so that the library binds to that same runtime.  Loaded the other way round, torch
+        # would find the system runtime already in the process and fail to initialise.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

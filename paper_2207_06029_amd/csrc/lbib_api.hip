@@ -104,11 +104,11 @@ lbib_status autotune(Batch& B, const char* cache) {
         if (st) return st;
         // sweeps from the current buffer into the other one; the state is not advanced
         for (int w = 0; w < 2; ++w)
-            launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tile_job.size(), c, B.xcd_chunk, B.stream);
+            launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tiles.size(), c, B.xcd_chunk, B.stream);
         if (hipEventRecord(ev.e0, B.stream) != hipSuccess) return fail(LBIB_EDEVICE, "autotune event record failed");
         const int reps = 8;
         for (int r = 0; r < reps; ++r)
-            launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tile_job.size(), c, B.xcd_chunk, B.stream);
+            launch_sweep(B.P, B.storage, true, !B.cur_b, (int)B.tiles.size(), c, B.xcd_chunk, B.stream);
         if (hipEventRecord(ev.e1, B.stream) != hipSuccess) return fail(LBIB_EDEVICE, "autotune event record failed");
         if (hipEventSynchronize(ev.e1) != hipSuccess) return fail(LBIB_EDEVICE, "autotune sync failed");
         float ms = 0.f;

@@ -81,7 +81,9 @@ struct JobDev {
     float wall_u[6][3];
     float G[3];           // uniform body force density
     int body0, nbodies;   // bodies living in this lattice
-    int pad0, pad1;
+    // v / nx and v / ny as multiply-high by these for v < 2^16 (ceil(2^32 / n), exact while
+    // v (2^32 mod' n) < 2^32, i.e. for dimensions below 2^15); 0 for larger dimensions
+    unsigned mx, my;
 };
 
 struct WinDesc {
@@ -136,7 +138,7 @@ struct Pools {
     void* popA;
     void* popB;
     const JobDev* jobs;
-    const int* tile_job;
+    const int4* tiles;       // per sweep tile: job, coordinates (x, y, z) of its first node
     const BodyDev* bodies;
     const int* blk_body_c;   // block -> body for the centroid kernel (triangle blocks)
     const int* blk_body_e;   // block -> body for the edge blocks of the centroid kernel
@@ -169,6 +171,9 @@ struct Pools {
     double* partial;         // block partial sums (16 doubles per block)
     int* vbox;               // [6 per vertex block] integer box (floor min, ceil max) of x^{n+1}
     int* flags;              // per job
+    unsigned* sr_ctr;        // per job, two slots (buffer A, B): step counter seeding the
+                             // stochastic narrowing of reduced-precision storage
+    int pop32;               // every job's populations span less than 4 GiB (32-bit offsets)
     int solo_job;            // job of the only body when the batch holds one body, else -1
     BodyDev solo_body;       // that body's record (valid when solo_job >= 0)
 };

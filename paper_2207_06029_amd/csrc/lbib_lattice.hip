@@ -14,22 +14,96 @@ namespace lbib {
 
 // ---------------------------------------------------------------- storage codecs
 template <typename S> struct Codec;
+// ld / st convert between the stored value and the deviation; raw / st_raw move the stored value
+// in storage units (the deviation times scale) for code that works in those units throughout.
 template <> struct Codec<float> {
+    static constexpr float scale = 1.0f;
     __device__ static __forceinline__ float ld(const float* p) { return *p; }
     __device__ static __forceinline__ void st(float* p, float v) { *p = v; }
+    __device__ static __forceinline__ float raw(const float* p) { return *p; }
+    __device__ static __forceinline__ void st_raw(float* p, float v) { *p = v; }
 };
 // FP16 holds the deviation times 2^12: an exact power-of-two scaling that keeps deviations
 // down to ~1.5e-8 in the normal range (full 11-bit precision) while |g| up to 16 still fits.
 constexpr float F16_SCALE = 4096.0f;
 constexpr float F16_INV = 1.0f / 4096.0f;
 template <> struct Codec<__half> {
+    static constexpr float scale = F16_SCALE;
     __device__ static __forceinline__ float ld(const __half* p) { return __half2float(*p) * F16_INV; }
     __device__ static __forceinline__ void st(__half* p, float v) { *p = __float2half_rn(v * F16_SCALE); }
+    __device__ static __forceinline__ float raw(const __half* p) { return __half2float(*p); }
+    __device__ static __forceinline__ void st_raw(__half* p, float v) { *p = __float2half_rn(v); }
 };
 template <> struct Codec<__hip_bfloat16> {
+    static constexpr float scale = 1.0f;
     __device__ static __forceinline__ float ld(const __hip_bfloat16* p) { return __bfloat162float(*p); }
     __device__ static __forceinline__ void st(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+    __device__ static __forceinline__ float raw(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+    __device__ static __forceinline__ void st_raw(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
 };
+
+// Stochastic rounding of the collision's output (the sweep's only narrowing that is repeated every
+// step).  Round-to-nearest of a slowly varying population loses every update smaller than half a
+// unit in the last place, the same way every step, so a flow developing from rest stagnates;
+// rounding up with probability equal to the dropped fraction keeps every update in expectation.
+// Before round-to-nearest the value x is moved by d * P(x), where P(x) is the power of two at or
+// below |x| (its exponent bits; 0 for zero and FP32 subnormals, which stay unperturbed) and d is
+// uniform over (-1/2, 1/2) of the target format's unit in the last place in 1/256 steps:
+// round-to-nearest then rounds up with probability equal to the dropped fraction, to within 1/256.
+template <typename S> struct Narrow;
+// cvt / st take the value in storage units.
+template <> struct Narrow<float> {
+    static constexpr float ulp = 0.f;
+    __device__ static __forceinline__ float cvt(float v, float) { return v; }
+    __device__ static __forceinline__ void st(float* p, float v, float) { *p = v; }
+};
+__device__ __forceinline__ float sr_perturb(float x, float d) {
+    return fmaf(d, __uint_as_float(__float_as_uint(x) & 0x7F800000u), x);
+}
+template <> struct Narrow<__half> {
+    static constexpr float ulp = 1.f / 1024.f;   // 10 stored mantissa bits
+    __device__ static __forceinline__ __half cvt(float v, float d) { return __float2half_rn(sr_perturb(v, d)); }
+    __device__ static __forceinline__ void st(__half* p, float v, float d) { *p = cvt(v, d); }
+};
+template <> struct Narrow<__hip_bfloat16> {
+    static constexpr float ulp = 1.f / 128.f;    // 7 stored mantissa bits
+    __device__ static __forceinline__ __hip_bfloat16 cvt(float v, float d) { return __float2bfloat16(sr_perturb(v, d)); }
+    __device__ static __forceinline__ void st(__hip_bfloat16* p, float v, float d) { *p = cvt(v, d); }
+};
+
+// Stores through a buffer resource over a job's populations (at most 4 GiB): the per-lane offset
+// of the node is shared by all planes, the plane's offset rides in a scalar register.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pop_rsrc(void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, __half v, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, __hip_bfloat16 v, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, 0);
+}
+
+// Counter-based random offsets of one node and step: a 32-bit integer hash (multiply-xorshift) of
+// the node index and the job's step counter, continued by one xorshift step; its eight bytes give
+// eight offsets d, and population i takes offset i mod 8.  A job's offsets depend only on its own
+// node indices and steps, so its results are the same alone and in any batch.
+__device__ __forceinline__ unsigned mix32(unsigned x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ unsigned xorshift32(unsigned x) {
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+}
 
 // ---------------------------------------------------------------- Zou-He closure
 // Wet wall node on the face of axis a: low face (side 0, inward normal +a) or high face
@@ -214,39 +288,73 @@ __device__ __forceinline__ void zou_he_corner(const JobDev& J, int s0, int s1, i
 }
 
 // ---------------------------------------------------------------- pull
+// Walls of job J: bit f (lbib_bc face order) set for a face that is not periodic; WALL_TERMS set
+// when some wall adds a term to the redirected populations (a moving bounce-back wall, or a
+// Zou-He wall whose unknowns are rebuilt).  Halfway bounce-back at rest is the redirect alone.
+constexpr unsigned WALL_TERMS = 64u;
+__device__ __forceinline__ unsigned wall_faces(const JobDev& J) {
+    unsigned m = 0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        m |= (J.bc[f] != 0 ? 1u : 0u) << f;
+        const bool moving = J.wall_u[f][0] != 0.f || J.wall_u[f][1] != 0.f || J.wall_u[f][2] != 0.f;
+        if (J.bc[f] == 1 || (J.bc[f] == 2 && moving)) m |= WALL_TERMS;
+    }
+    return m;
+}
+
 // Post-streaming deviations at node (x, y, z) of job J from the post-collision buffer src.
 // All 19 loads are issued unconditionally, so they are in flight together: a source outside
 // the domain is redirected to the node's own opposite population (the halfway bounce-back
 // source, always a valid address), and the wall term or the Zou-He closure is applied once
 // the loads have returned.  Without ZH_CLOSURE the populations of Zou-He wall nodes stay
 // unclosed (finite but meaningless): for readers that never look at those nodes.
-template <typename S, bool ZH_CLOSURE = true>
+
+template <typename S, bool ZH_CLOSURE = true, bool OFF32 = false, bool RAW = false>
 __device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J, int x, int y,
-                                     int z, long long k, float g[Q]) {
+                                     int z, long long k, float g[Q], unsigned walls) {
     const long long N = J.n;
     const int nx = J.nx, ny = J.ny, nz = J.nz;
     const int sy = nx, sz = nx * ny;
-    // linear displacement of the source for e = +1 (node c - 1) and e = -1 (node c + 1)
-    int dxm = -1, dxp = 1, dym = -sy, dyp = sy, dzm = -sz, dzp = sz;
-    bool oxm = false, oxp = false, oym = false, oyp = false, ozm = false, ozp = false;
-    if (x == 0) { if (J.bc[0] == 0) dxm = nx - 1; else oxm = true; }
-    if (x == nx - 1) { if (J.bc[1] == 0) dxp = 1 - nx; else oxp = true; }
-    if (y == 0) { if (J.bc[2] == 0) dym = (ny - 1) * sy; else oym = true; }
-    if (y == ny - 1) { if (J.bc[3] == 0) dyp = (1 - ny) * sy; else oyp = true; }
-    if (z == 0) { if (J.bc[4] == 0) dzm = (nz - 1) * sz; else ozm = true; }
-    if (z == nz - 1) { if (J.bc[5] == 0) dzp = (1 - nz) * sz; else ozp = true; }
+    // linear displacement of the source for e = +1 (node c - 1) and e = -1 (node c + 1): a
+    // neighbour across a periodic face wraps; across a wall the source is redirected (flags)
+    const bool lx = x == 0, hx = x == nx - 1, ly = y == 0, hy = y == ny - 1, lz = z == 0, hz = z == nz - 1;
+    const bool oxm = lx & ((walls & 1u) != 0), oxp = hx & ((walls & 2u) != 0);
+    const bool oym = ly & ((walls & 4u) != 0), oyp = hy & ((walls & 8u) != 0);
+    const bool ozm = lz & ((walls & 16u) != 0), ozp = hz & ((walls & 32u) != 0);
+    const int dxm = (lx & !oxm) ? nx - 1 : -1, dxp = (hx & !oxp) ? 1 - nx : 1;
+    const int dym = (ly & !oym) ? (ny - 1) * sy : -sy, dyp = (hy & !oyp) ? (1 - ny) * sy : sy;
+    const int dzm = (lz & !ozm) ? (nz - 1) * sz : -sz, dzp = (hz & !ozp) ? (1 - nz) * sz : sz;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int e0 = cx(i), e1 = cy(i), e2 = cz(i);
         const int d = (e0 == 1 ? dxm : (e0 == -1 ? dxp : 0)) + (e1 == 1 ? dym : (e1 == -1 ? dyp : 0)) +
                       (e2 == 1 ? dzm : (e2 == -1 ? dzp : 0));
-        const bool o = (e0 == 1 ? oxm : (e0 == -1 ? oxp : false)) ||
-                       (e1 == 1 ? oym : (e1 == -1 ? oyp : false)) ||
+        // bitwise or: no short-circuit branches, the redirect is a per-lane select
+        const bool o = (e0 == 1 ? oxm : (e0 == -1 ? oxp : false)) |
+                       (e1 == 1 ? oym : (e1 == -1 ? oyp : false)) |
                        (e2 == 1 ? ozm : (e2 == -1 ? ozp : false));
-        const long long idx = o ? (long long)opp(i) * N + k : (long long)i * N + k + d;
-        g[i] = Codec<S>::ld(src + idx);
+        if (OFF32) {
+            // the job's populations span less than 4 GiB: one 32-bit byte offset per load
+            const unsigned pb = (unsigned)N * (unsigned)sizeof(S), kb = (unsigned)k * (unsigned)sizeof(S);
+            unsigned alt = (unsigned)opp(i) * pb + kb, nrm = (unsigned)i * pb + kb + (unsigned)(d * (int)sizeof(S));
+            // both offsets are formed in registers: a lane select, not a branch around either sum
+            asm("" : "+v"(alt));
+            asm("" : "+v"(nrm));
+            const S* p = (const S*)((const char*)src + (o ? alt : nrm));
+            g[i] = RAW ? Codec<S>::raw(p) : Codec<S>::ld(p);
+        } else {
+            const long long idx = o ? (long long)opp(i) * N + k : (long long)i * N + k + d;
+            g[i] = RAW ? Codec<S>::raw(src + idx) : Codec<S>::ld(src + idx);
+        }
     }
-    if (!(oxm || oxp || oym || oyp || ozm || ozp)) return;
+    if (!(walls & WALL_TERMS) || !(oxm || oxp || oym || oyp || ozm || ozp)) return;
+    // the wall terms are formed on deviations (exact power-of-two rescaling of raw values)
+    constexpr bool RESCALE = RAW && Codec<S>::scale != 1.0f;
+    if (RESCALE) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g[i] *= 1.0f / Codec<S>::scale;
+    }
     // face kinds and wall velocities are uniform over the job: select among them per lane
     bool bb[6];
 #pragma unroll
@@ -284,7 +392,12 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J,
             zou_he_corner(J, s0, s1, s2, g);
         }
     }
+    if (RESCALE) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g[i] *= Codec<S>::scale;
+    }
 }
+
 
 __device__ __forceinline__ void node_coords(const JobDev& J, long long k, int& x, int& y, int& z) {
     const unsigned kk = (unsigned)k;
@@ -321,55 +434,201 @@ __device__ __forceinline__ void node_force(const Pools& P, const JobDev& J, int 
 }
 
 // ---------------------------------------------------------------- fused sweep
-// One node: pull, moments, body force, BGK collision with Guo forcing (all on deviations),
-// store.  With COLLIDE false the pulled values are stored unchanged (pure streaming).
-template <typename S, bool COLLIDE>
-__device__ __forceinline__ void sweep_node(const Pools& P, const JobDev& J, const S* __restrict__ src,
-                                           S* __restrict__ dst, long long k, int job) {
-    int x, y, z;
-    node_coords(J, k, x, y, z);
-    float g[Q];
-    pull<S>(src, J, x, y, z, k, g);
-    const long long N = J.n;
-    if (COLLIDE) {
-        float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+// Force window of a lattice's only body, read once per block, before the block's first store.
+struct Win1 {
+    int o[3], w[3];
+    long long capn;
+    const long long* fw;
+    bool valid;
+};
+
+__device__ __forceinline__ Win1 load_win1(const Pools& P, const JobDev& J) {
+    Win1 W;
+    const int b = J.body0;
+    const WinDesc d = P.fdesc[b];
+    const BodyDev& B = P.bodies[b];
+    const int dims[3] = {J.nx, J.ny, J.nz};
+    W.valid = win_valid(d, dims, B.win_cap, J.bc);
+    for (int a = 0; a < 3; ++a) { W.o[a] = d.o[a]; W.w[a] = d.w[a]; }
+    W.capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+    W.fw = P.fwin + 3 * B.win_off;
+    return W;
+}
+
+// Body force at a node: uniform G plus the fixed-point immersed-boundary force of the window that
+// holds the node (one body: W; more: every body's window in turn).
+__device__ __forceinline__ void sweep_force(const Pools& P, const JobDev& J, const Win1& W, int x, int y,
+                                            int z, float F[3]) {
+    F[0] = J.G[0]; F[1] = J.G[1]; F[2] = J.G[2];
+    if (J.nbodies == 0) return;
+    if (J.nbodies > 1) { node_force(P, J, x, y, z, F); return; }
+    if (!W.valid) return;
+    int lx = x - W.o[0], ly = y - W.o[1], lz = z - W.o[2];
+    if (lx < 0) lx += J.nx;
+    if (ly < 0) ly += J.ny;
+    if (lz < 0) lz += J.nz;
+    if (lx < W.w[0] && ly < W.w[1] && lz < W.w[2]) {
+        const unsigned l = (unsigned)lx + (unsigned)W.w[0] * ((unsigned)ly + (unsigned)W.w[1] * (unsigned)lz);
+        const long long* fw = W.fw + l;
+        F[0] += (float)((double)fw[0] * FIX_INV);
+        F[1] += (float)((double)fw[W.capn] * FIX_INV);
+        F[2] += (float)((double)fw[2 * W.capn] * FIX_INV);
+    }
+}
+
+// BGK relaxation with Guo forcing (Eqs. (2)-(4) on deviations g = f - w) of one node's pulled
+// populations, in storage units (the deviation times SC, an exact power of two): the equilibrium
+// and forcing terms carry the factor SC in their weights.  Opposite populations i and i' share
+// e.u, e.F and the even parts of both terms, which enter with the opposite sign for the odd
+// parts: per pair, the equilibrium is w (a + b) for i and w (a - b) for i', the forcing C + D and
+// C - D.  The weight multiplies the sum last, as in the per-population form: a weight applied to
+// rho or drho first (w rho, w drho) rounds the same way at every node of a near-unit density and
+// biases the equilibrium, an error that grows with the step count instead of averaging out.
+// Without FORCED the force is zero at every lane (the forcing terms vanish).  Each result goes to
+// emit(i, value) as soon as it is formed.
+template <typename S, bool FORCED, typename Emit>
+__device__ __forceinline__ void bgk_guo(const float g[Q], float drho, float rho, float ux, float uy, float uz,
+                                        const float F[3], float om, float gk, Emit emit) {
+    constexpr float SC = Codec<S>::scale;
+    const float mu = -1.5f * (ux * ux + uy * uy + uz * uz);
+    const float muF = FORCED ? -3.f * (ux * F[0] + uy * F[1] + uz * F[2]) : 0.f;
+    {
+        const float w = SC * (float)wq(0);
+        const float geq = w * (drho + rho * mu);
+        float v = g[0] - om * (g[0] - geq);
+        if (FORCED) v += gk * w * muF;
+        emit(0, v);
+    }
+    const float rho3 = 3.f * rho;
+    // forcing weights per class (axis, diagonal): 3 gk w, 9 gk w, gk w (-3 u.F)
+    float gw3[2], gw9[2], gmu[2];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            drho += g[i];
-            if (cx(i)) jx += cx(i) * g[i];
-            if (cy(i)) jy += cy(i) * g[i];
-            if (cz(i)) jz += cz(i) * g[i];
+    for (int c = 0; c < 2; ++c) {
+        if (FORCED) {
+            const float gw = gk * (SC * (float)wq(c == 0 ? 1 : 7));
+            gw3[c] = 3.f * gw;
+            gw9[c] = 9.f * gw;
+            gmu[c] = gw * muF;
         }
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int o = opp(i);
+        if (o < i) continue;   // i is the first of its pair
+        const int c = i <= 6 ? 0 : 1;
+        const float w = SC * (float)wq(i);
+        const float eu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+        const float a = fmaf(rho, fmaf(4.5f * eu, eu, mu), drho);
+        const float b = rho3 * eu;
+        float vp = g[i] - om * (g[i] - w * (a + b));
+        float vm = g[o] - om * (g[o] - w * (a - b));
+        if (FORCED) {
+            const float eF = cx(i) * F[0] + cy(i) * F[1] + cz(i) * F[2];
+            const float C = fmaf(gw9[c] * eu, eF, gmu[c]);
+            const float D = gw3[c] * eF;
+            vp += C + D;
+            vm += C - D;
+        }
+        emit(i, vp);
+        emit(o, vm);
+    }
+}
+
+// One node: pull, moments, body force, BGK collision with Guo forcing (all on deviations),
+// store.  With COLLIDE false the pulled values are stored unchanged (pure streaming).  Stores go to
+// the population planes through a 32-bit byte offset of the node (the same for every plane).
+// Populations stay in storage units from load to store; the moments are scaled back exactly.
+template <typename S, bool COLLIDE, bool OFF32>
+__device__ __forceinline__ void sweep_node(const Pools& P, const JobDev& J, const Win1& W,
+                                           const S* __restrict__ src, S* __restrict__ dst, long long k,
+                                           int x, int y, int z, int job, unsigned seed, unsigned walls) {
+    float g[Q];
+    pull<S, true, OFF32, true>(src, J, x, y, z, k, g, walls);
+    const long long N = J.n;
+    const unsigned kb = (unsigned)k * (unsigned)sizeof(S);
+    const long long pb = N * (long long)sizeof(S);   // bytes per population plane
+    char* plane = (char*)dst;                         // plane i of the destination, stepped by pb
+    const __amdgpu_buffer_rsrc_t rs = pop_rsrc(dst, OFF32 ? (unsigned)(Q * pb) : 0u);
+    if (COLLIDE) {
+        constexpr float ISC = 1.0f / Codec<S>::scale;
+        // moments from the sums and differences of opposite pairs
+        float ds = g[0], jxs = 0.f, jys = 0.f, jzs = 0.f;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int o = opp(i);
+            if (o < i) continue;
+            const float sp = g[i] + g[o], dp = g[i] - g[o];
+            ds += sp;
+            if (cx(i)) jxs += cx(i) * dp;
+            if (cy(i)) jys += cy(i) * dp;
+            if (cz(i)) jzs += cz(i) * dp;
+        }
+        const float drho = ds * ISC, jx = jxs * ISC, jy = jys * ISC, jz = jzs * ISC;
         float F[3];
-        if (J.nbodies) node_force(P, J, x, y, z, F);
-        else { F[0] = J.G[0]; F[1] = J.G[1]; F[2] = J.G[2]; }
+        sweep_force(P, J, W, x, y, z, F);
         const float rho = 1.f + drho;
         const float ir = 1.f / rho;
         const float ux = (jx + 0.5f * F[0]) * ir;
         const float uy = (jy + 0.5f * F[1]) * ir;
         const float uz = (jz + 0.5f * F[2]) * ir;
-        const float uu = ux * ux + uy * uy + uz * uz;
-        const float uF = ux * F[0] + uy * F[1] + uz * F[2];
         const float om = J.omega, gk = J.guo;
         // runaway sentinel: non-finite, or a density no flow of the scheme reaches (the singular
         // lid edges of a cavity at lid Mach 0.6 reach about 2.7)
         if (!(drho > -0.95f && drho < 7.f)) atomicOr(P.flags + job, FLAG_NONFINITE);
+        // FP32: each result is stored as soon as it is formed (plane i at byte i * pb).  Narrow
+        // types gather the results first: the offsets of the stochastic narrowing are drawn after
+        // the collision, so they do not hold registers through it.
+        constexpr bool DIRECT = sizeof(S) == 4;
+        float out[Q];
+        const auto emit = [&](int i, float v) {
+            if (DIRECT) {
+                if (OFF32) buf_st(rs, Narrow<S>::cvt(v, 0.f), kb, (unsigned)i * (unsigned)pb);
+                else Narrow<S>::st((S*)((char*)dst + (long long)i * pb + kb), v, 0.f);
+            } else {
+                out[i] = v;
+            }
+        };
+        // the forcing terms are formed only in waves where some node carries a force
+        if (__any(F[0] != 0.f || F[1] != 0.f || F[2] != 0.f))
+            bgk_guo<S, true>(g, drho, rho, ux, uy, uz, F, om, gk, emit);
+        else
+            bgk_guo<S, false>(g, drho, rho, ux, uy, uz, F, om, gk, emit);
+        if (!DIRECT) {
+            // offsets of the stochastic narrowing
+            float dof[8];
+            unsigned rw[2];
+            rw[0] = mix32((unsigned)k * 0x9E3779B9U ^ seed);
+            rw[1] = xorshift32(rw[0]);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const float w = (float)wq(i);
-            const float eu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-            const float eF = cx(i) * F[0] + cy(i) * F[1] + cz(i) * F[2];
-            const float geq = w * (drho + rho * (3.f * eu + 4.5f * eu * eu - 1.5f * uu));
-            const float Fi = gk * w * (3.f * (eF - uF) + 9.f * eu * eF);
-            Codec<S>::st(dst + (long long)i * N + k, g[i] - om * (g[i] - geq) + Fi);
+            for (int q = 0; q < 8; ++q) {
+                const int r = (int)(rw[q / 4] << (24 - 8 * (q % 4))) >> 24;   // -128..127
+                // (r + 1/2) ulp / 256, exact (the step is a power of two)
+                dof[q] = fmaf((float)r, Narrow<S>::ulp * (1.f / 256.f), Narrow<S>::ulp * (0.5f / 256.f));
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (OFF32) {
+                    buf_st(rs, Narrow<S>::cvt(out[i], dof[i % 8]), kb, (unsigned)i * (unsigned)pb);
+                } else {
+                    Narrow<S>::st((S*)(plane + kb), out[i], dof[i % 8]);
+                    plane += pb;
+                }
+            }
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) Codec<S>::st(dst + (long long)i * N + k, g[i]);
+        for (int i = 0; i < Q; ++i) {
+            if (OFF32) {
+                buf_st(rs, Narrow<S>::cvt(g[i], 0.f), kb, (unsigned)i * (unsigned)pb);
+            } else {
+                Codec<S>::st_raw((S*)(plane + kb), g[i]);
+                plane += pb;
+            }
+        }
     }
 }
 
-template <typename S, bool COLLIDE, int NPT>
+template <typename S, bool COLLIDE, int NPT, bool OFF32>
 __global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b, int xcd_chunk) {
     // The dispatcher deals consecutive blocks to the 8 XCDs in turn, each with its own L2.
     // With xcd_chunk = C > 0 the blocks are remapped so that every XCD takes C consecutive
@@ -381,36 +640,66 @@ __global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b, int xcd_chu
         const int span = 8 * xcd_chunk;
         if (bid < (T / span) * span) tile = (bid / span) * span + (bid & 7) * xcd_chunk + (bid >> 3) % xcd_chunk;
     }
-    const int job = P.tile_job[tile];
+    const int4 te = P.tiles[tile];
+    const int job = te.x;
     const JobDev& J = P.jobs[job];
     const S* src = (const S*)(a_to_b ? P.popA : P.popB) + J.pop_off;
     S* dst = (S*)(a_to_b ? P.popB : P.popA) + J.pop_off;
     const long long base = (long long)(tile - J.tile0) * blockDim.x * NPT;
+    Win1 W = {};
+    if (COLLIDE && J.nbodies == 1) W = load_win1(P, J);
+    const unsigned nx = (unsigned)J.nx, ny = (unsigned)J.ny, mx = J.mx, my = J.my;
+    const unsigned walls = wall_faces(J);
+    // the job's step counter of the buffer being read seeds the stochastic narrowing; the block of
+    // the job's first tile hands the next value to the other buffer's slot, read by the next step
+    unsigned seed = 0;
+    if (COLLIDE && sizeof(S) < 4) {
+        const unsigned* ctr = P.sr_ctr + 2 * job;
+        const unsigned c = ctr[a_to_b ? 0 : 1];
+        if (tile == J.tile0 && threadIdx.x == 0) P.sr_ctr[2 * job + (a_to_b ? 1 : 0)] = c + 1;
+        seed = mix32(c + 0x632BE5ABU);
+    }
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
+        // coordinates from those of the tile's first node (tile table): row and plane carries by
+        // multiply-high with the job's reciprocals (exact for these small numerators)
         const long long k = base + (long long)r * blockDim.x + threadIdx.x;
-        if (k < J.n) sweep_node<S, COLLIDE>(P, J, src, dst, k, job);
+        if (k >= J.n) continue;
+        const unsigned x0 = (unsigned)te.y, y0 = (unsigned)te.z, z0 = (unsigned)te.w;
+        const unsigned xs = x0 + (unsigned)(r * blockDim.x) + threadIdx.x;
+        const unsigned qx = mx ? __umulhi(xs, mx) : xs / nx;
+        const unsigned ys = y0 + qx;
+        const unsigned qy = my ? __umulhi(ys, my) : ys / ny;
+        sweep_node<S, COLLIDE, OFF32>(P, J, W, src, dst, k, (int)(xs - qx * nx), (int)(ys - qy * ny), (int)(z0 + qy),
+                               job, seed, walls);
     }
 }
 
-template <typename S, bool C, int NPT>
+template <typename S, bool C, int NPT, bool OFF32>
 static void sweep_n(const Pools& P, bool a_to_b, int chunk, dim3 grid, dim3 block, hipStream_t s,
                     hipEvent_t ev0, hipEvent_t ev1) {
     if (ev0 || ev1)
-        hipExtLaunchKernelGGL((k_sweep<S, C, NPT>), grid, block, 0, s, ev0, ev1, 0, P, (int)a_to_b, chunk);
+        hipExtLaunchKernelGGL((k_sweep<S, C, NPT, OFF32>), grid, block, 0, s, ev0, ev1, 0, P, (int)a_to_b, chunk);
     else
-        hipLaunchKernelGGL((k_sweep<S, C, NPT>), grid, block, 0, s, P, (int)a_to_b, chunk);
+        hipLaunchKernelGGL((k_sweep<S, C, NPT, OFF32>), grid, block, 0, s, P, (int)a_to_b, chunk);
+}
+
+template <typename S, bool C, bool OFF32>
+static void sweep_o(const Pools& P, bool a_to_b, int ntiles, SweepShape sh, int chunk, hipStream_t s,
+                    hipEvent_t ev0, hipEvent_t ev1) {
+    dim3 grid(ntiles), block(sh.block);
+    switch (sh.npt) {
+        case 1: sweep_n<S, C, 1, OFF32>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
+        case 2: sweep_n<S, C, 2, OFF32>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
+        default: sweep_n<S, C, 4, OFF32>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
+    }
 }
 
 template <typename S, bool C>
 static void sweep_t(const Pools& P, bool a_to_b, int ntiles, SweepShape sh, int chunk, hipStream_t s,
                     hipEvent_t ev0, hipEvent_t ev1) {
-    dim3 grid(ntiles), block(sh.block);
-    switch (sh.npt) {
-        case 1: sweep_n<S, C, 1>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
-        case 2: sweep_n<S, C, 2>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
-        default: sweep_n<S, C, 4>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
-    }
+    if (P.pop32) sweep_o<S, C, true>(P, a_to_b, ntiles, sh, chunk, s, ev0, ev1);
+    else sweep_o<S, C, false>(P, a_to_b, ntiles, sh, chunk, s, ev0, ev1);
 }
 
 void launch_sweep(const Pools& P, int storage, bool collide, bool a_to_b, int ntiles,
@@ -460,7 +749,7 @@ __global__ void __launch_bounds__(256) k_window_moments(Pools P, int from_b) {
         // MLS supports exclude Zou-He wall nodes (their moments are never read), so the pull
         // skips the Zou-He closure here
         float g[Q];
-        pull<S, false>(src, J, x, y, z, k, g);
+        pull<S, false>(src, J, x, y, z, k, g, wall_faces(J));
         float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -503,7 +792,7 @@ __device__ __forceinline__ float4 node_moments(const Pools& P, const JobDev& J, 
     node_coords(J, k, x, y, z);
     const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
     float g[Q];
-    pull<S>(src, J, x, y, z, k, g);
+    pull<S>(src, J, x, y, z, k, g, wall_faces(J));
     float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -549,7 +838,7 @@ __global__ void k_get_pop_plane(Pools P, int from_b, int job, int plane, double*
     node_coords(J, k, x, y, z);
     const S* src = (const S*)(from_b ? P.popB : P.popA) + J.pop_off;
     float g[Q];
-    pull<S>(src, J, x, y, z, k, g);
+    pull<S>(src, J, x, y, z, k, g, wall_faces(J));
     float gi = g[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i)

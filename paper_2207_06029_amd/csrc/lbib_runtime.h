@@ -60,8 +60,8 @@ struct Batch {
     size_t mark_used = 0, mark_owned = 0;
     std::vector<lbib_lattice_desc> ldesc;
     std::vector<JobDev> jobs;
-    std::vector<int> tile_job;
-    int* d_tile_job = nullptr;     // from the arena, tile_cap entries
+    std::vector<int4> tiles;       // per sweep tile: job, coordinates of its first node
+    int4* d_tiles = nullptr;       // from the arena, tile_cap entries
     size_t tile_cap = 0;
     double* d_totals = nullptr;    // 6 doubles: membrane force/torque totals on their way out
     JobDev* d_jobs = nullptr;
@@ -104,6 +104,8 @@ struct Batch {
                          const int* tri, int nt, int* id);
     int body_index(int job, int local) const;
     void* spare(int job) const;
+    // step counter seeding the job's stochastic narrowing (both buffer slots)
+    lbib_status set_step_counter(int job, unsigned value);
     lbib_status init_job(int job, const double* rho, const double* u);
     lbib_status set_populations(int job, const double* f);
     lbib_status get_macros(int job, double* rho, double* u);

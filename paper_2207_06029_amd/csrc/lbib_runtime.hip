@@ -124,8 +124,8 @@ lbib_status check_lattice(const lbib_lattice_desc& d) {
 size_t workspace_need(const lbib_lattice_desc& d, long long nv, long long nt) {
     auto r = [](long long bytes) -> size_t { return (size_t)((std::max<long long>(bytes, 1) + 255) & ~255LL); };
     const long long n = (long long)d.nx * d.ny * d.nz;
-    size_t b = 2 * r(19 * n * (long long)storage_bytes(d.storage)) + r(sizeof(int)) + r(sizeof(JobDev)) +
-               r(sizeof(int) * ((n + MIN_TILE_NODES - 1) / MIN_TILE_NODES));
+    size_t b = 2 * r(19 * n * (long long)storage_bytes(d.storage)) + r(sizeof(int)) + r(2 * sizeof(unsigned)) +
+               r(sizeof(JobDev)) + r(sizeof(int4) * ((n + MIN_TILE_NODES - 1) / MIN_TILE_NODES));
     const bool body = nv > 0;
     if (!body) nv = nt = 0;
     const long long ne = 3 * nt / 2;
@@ -389,6 +389,8 @@ void Batch::job_from_desc(const lbib_lattice_desc& d, JobDev& J) {
     for (int a = 0; a < 3; ++a)
         if (d.bc[2 * a] == 1 || d.bc[2 * a + 1] == 1) ++J.zh_axes;
     for (int a = 0; a < 3; ++a) J.G[a] = (float)d.body_force[a];
+    J.mx = d.nx < (1 << 15) ? (unsigned)((0x100000000ULL + d.nx - 1) / d.nx) : 0u;
+    J.my = d.ny < (1 << 15) ? (unsigned)((0x100000000ULL + d.ny - 1) / d.ny) : 0u;
 }
 
 lbib_status Batch::create_lattices(const std::vector<lbib_lattice_desc>& descs, int storage_,
@@ -410,6 +412,9 @@ lbib_status Batch::create_lattices(const std::vector<lbib_lattice_desc>& descs, 
         jobs[j].nbodies = 0;
     }
     pop_elems = off;
+    P.pop32 = 1;
+    for (auto& J : jobs)
+        if (19LL * J.n * storage_bytes(storage) >= (1LL << 32)) P.pop32 = 0;
     lbib_status st = arena.alloc(pop_elems * storage_bytes(storage), &P.popA);
     if (st) return st;
     if ((st = arena.alloc(pop_elems * storage_bytes(storage), &P.popB))) return st;
@@ -417,14 +422,17 @@ lbib_status Batch::create_lattices(const std::vector<lbib_lattice_desc>& descs, 
     if ((st = arena.alloc(sizeof(int) * jobs.size(), &p))) return st;
     P.flags = (int*)p;
     HIP_TRY(hipMemsetAsync(P.flags, 0, sizeof(int) * jobs.size(), stream));
+    if ((st = arena.alloc(sizeof(unsigned) * 2 * jobs.size(), &p))) return st;
+    P.sr_ctr = (unsigned*)p;
+    HIP_TRY(hipMemsetAsync(P.sr_ctr, 0, sizeof(unsigned) * 2 * jobs.size(), stream));
     if ((st = arena.alloc(sizeof(JobDev) * jobs.size(), &p))) return st;
     d_jobs = (JobDev*)p;
     P.jobs = d_jobs;
     // sweep tile table, sized for the smallest tile any launch shape uses
     tile_cap = 0;
     for (auto& J : jobs) tile_cap += (size_t)((J.n + MIN_TILE_NODES - 1) / MIN_TILE_NODES);
-    if ((st = arena.alloc(sizeof(int) * std::max<size_t>(tile_cap, 1), &p))) return st;
-    d_tile_job = (int*)p;
+    if ((st = arena.alloc(sizeof(int4) * std::max<size_t>(tile_cap, 1), &p))) return st;
+    d_tiles = (int4*)p;
     mark_used = arena.used;
     mark_owned = arena.owned.size();
     if ((st = retile())) return st;
@@ -437,21 +445,24 @@ lbib_status Batch::create_lattices(const std::vector<lbib_lattice_desc>& descs, 
 
 // Tile list of the sweep for the current launch shape.
 lbib_status Batch::retile() {
-    tile_job.clear();
+    tiles.clear();
     const long long per = (long long)shape.block * shape.npt;
     long long pop_bytes = 0;
     for (size_t j = 0; j < jobs.size(); ++j) {
-        jobs[j].tile0 = (int)tile_job.size();
+        jobs[j].tile0 = (int)tiles.size();
         jobs[j].ntiles = (int)((jobs[j].n + per - 1) / per);
-        for (int t = 0; t < jobs[j].ntiles; ++t) tile_job.push_back((int)j);
+        for (int t = 0; t < jobs[j].ntiles; ++t) {
+            const long long k0 = (long long)t * per, q = k0 / jobs[j].nx;
+            tiles.push_back(make_int4((int)j, (int)(k0 - q * jobs[j].nx), (int)(q % jobs[j].ny), (int)(q / jobs[j].ny)));
+        }
         pop_bytes += 2LL * Q * (long long)storage_bytes(storage) * jobs[j].n;
     }
     xcd_chunk = shape.xcd_chunk >= 0 ? shape.xcd_chunk : (pop_bytes <= XCD_CHUNK_MAX_BYTES ? XCD_CHUNK : 0);
-    if (tile_job.size() > tile_cap)
+    if (tiles.size() > tile_cap)
         return fail(LBIB_EINVAL, "sweep launch shape below " + std::to_string(MIN_TILE_NODES) + " nodes per tile");
     HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(JobDev) * jobs.size(), hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(d_tile_job, tile_job.data(), sizeof(int) * tile_job.size(), hipMemcpyHostToDevice, stream));
-    P.tile_job = d_tile_job;
+    HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, stream));
+    P.tiles = d_tiles;
     graph_valid = false;
     return LBIB_OK;
 }
@@ -685,6 +696,13 @@ int Batch::body_index(int job, int local) const {
 // The population buffer that does not hold the current state: its region of a job is dead
 // until the next sweep overwrites it, so host transfers stage through it (19 n s bytes per
 // job: at least 38 bytes per node) and no call needs device memory of its own.
+lbib_status Batch::set_step_counter(int job, unsigned value) {
+    const unsigned v[2] = {value, value};
+    HIP_TRY(hipMemcpyAsync(P.sr_ctr + 2 * job, v, sizeof v, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return LBIB_OK;
+}
+
 void* Batch::spare(int job) const {
     return (char*)(cur_b ? P.popA : P.popB) + jobs[job].pop_off * storage_bytes(storage);
 }
@@ -698,6 +716,7 @@ lbib_status Batch::init_job(int job, const double* rho, const double* u) {
     if (u) HIP_TRY(hipMemcpyAsync(du, u, sizeof(double) * 3 * n, hipMemcpyHostToDevice, stream));
     launch_init_eq(P, storage, cur_b, job, n, drho, du, stream);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemsetAsync(P.sr_ctr + 2 * job, 0, 2 * sizeof(unsigned), stream));
     HIP_TRY(hipStreamSynchronize(stream));
     primed = false;
     step_count = 0;
@@ -783,10 +802,10 @@ lbib_status Batch::enqueue_step(bool collide) {
         lbib_status st = next_event(&a);
         if (!st) st = next_event(&b);
         if (st) return st;
-        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, xcd_chunk, stream, a, b);
+        launch_sweep(P, storage, collide, !cur_b, (int)tiles.size(), shape, xcd_chunk, stream, a, b);
         sweep_events.push_back({a, b});
     } else {
-        launch_sweep(P, storage, collide, !cur_b, (int)tile_job.size(), shape, xcd_chunk, stream);
+        launch_sweep(P, storage, collide, !cur_b, (int)tiles.size(), shape, xcd_chunk, stream);
     }
     cur_b = !cur_b;
     if (bodies) {

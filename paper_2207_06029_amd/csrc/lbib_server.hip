@@ -106,6 +106,9 @@ lbib_status rebuild(lbib_server* S) {
             void* dst = (char*)(nb->cur_b ? nb->P.popB : nb->P.popA) + nb->jobs[k].pop_off * es;
             if (hipMemcpyAsync(dst, src, 19ull * oj.n * es, hipMemcpyDeviceToDevice, S->stream) != hipSuccess)
                 return fail(LBIB_EDEVICE, "state copy failed");
+            // the step counter seeding the stochastic narrowing carries over, so the job continues
+            // exactly as it would alone
+            if ((st = nb->set_step_counter((int)k, (unsigned)j.done))) return st;
             // carry the body
             for (auto& hb : ob.hbodies)
                 if (hb.job == j.slot_job) {
