@@ -8,10 +8,17 @@ spreading, the fused collide+stream sweep, window moments, probe stresses and th
 update (all HIP kernels of the library).  value = lattice node updates per second (MLUPS) over
 the timed steps.  The sweep's average launch duration comes from start/end events stamped by
 every sweep launch's own dispatch packet on the lattice's stream inside the timed region.
-`--workload prolate256` runs the same physics at 256x128x256 (level-5 mesh), a working set
-larger than the Infinity Cache; `--workload settling384` the 96x96x384 closed box with a rigid
-settling sphere in FP16 shifted storage (working set 269 MB).  `--mode batch` and `--mode serve` run the batched and served
-forms (64 capsule jobs; a Poisson stream of capsule and settling jobs).
+The headline case's populations (2 x 79.7 MB) fit the 256 MB Infinity Cache, so the same run
+also reports, under "extra", each with its own sweep fraction of the HBM roofline and its
+full-step fraction of roofline MLUPS: the same physics at 256x128x256 (level-5 mesh, 1.27 GB of
+populations), the 96x96x384 closed box with a rigid settling sphere in FP16 shifted storage
+(269 MB), and the 64-job FP16 batch against the same jobs one at a time in FP32 (jobs/h).
+`cpu_baseline` times the FP64 oracle on the host's cores and on one thread (headline case,
+32^3 capsule and settling box), with the CPU model and core count.
+
+`--workload prolate256 | settling384` makes one of the extra cases the headline; `--mode batch`
+and `--mode serve` run the batched and served forms alone (64 capsule jobs; a Poisson stream of
+capsule and settling jobs).
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
@@ -29,25 +36,29 @@ if ROOT not in sys.path:
 
 METRIC = "fused D3Q19+IB MLUPS & HBM-roofline %; batched jobs/h, p50/p99 latency"
 PEAK_HBM_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 << 20
+# the extra workloads of a default run take at least this many timed / warm-up steps
+EXTRA_MIN_STEPS = 200
+EXTRA_MIN_WARMUP = 20
 
-# HBM bytes per launch of the FP32 sweep on the 128x64x128 case, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters scaled by a plain copy of known size (fetch x2.0, write x1.0).  Reported
-# only while the sweep's sources hash to the value they had when the counters were taken.
 # every 10th sweep launch of the timed region carries start/end events (evenly spread; the
 # events' own cost stays out of the other steps)
 TIMING_PERIOD = 10
+# HBM bytes per launch of the sweep of each workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# counters scaled by a plain copy of known size (fetch x2.0, write x1.0).  Reported only while the
+# sweep's sources hash to the value they had when the counters were taken.
 SWEEP_SOURCES = ("paper_2207_06029_amd/csrc/lbib_lattice.hip", "paper_2207_06029_amd/csrc/lbib_internal.h")
 SWEEP_TRAFFIC = {
-    # FETCH_SIZE 39,272.2 KiB x 2.0 + WRITE_SIZE 77,824.0 KiB x 1.0 per dispatch
-    "prolate128": {"sha256": "ee6bce77e602b0664cba62131773ab5519d11e4d65284433acfc148a62bd137e",
-                   "bytes": 160121242},
-    # FETCH_SIZE 313,582.6 KiB x 2.0 + WRITE_SIZE 622,592.0 KiB x 1.0 per dispatch
-    "prolate256": {"sha256": "ee6bce77e602b0664cba62131773ab5519d11e4d65284433acfc148a62bd137e",
-                   "bytes": 1279751373},
-    # FETCH_SIZE 89,838.1 KiB x 2.0 + WRITE_SIZE 131,328.0 KiB x 1.0 per dispatch (the FP16
-    # reads are 1.36x their algorithmic bytes, probably since 192 B rows misalign the y-shifted streams)
-    "settling384": {"sha256": "ee6bce77e602b0664cba62131773ab5519d11e4d65284433acfc148a62bd137e",
-                    "bytes": 318468301},
+    # FETCH_SIZE 39,215.2 KiB x 2.0 + WRITE_SIZE 77,824.0 KiB x 1.0 per dispatch
+    "prolate128": {"sha256": "d35bd89596a0242ba1a0d47242e2dba8823d0abd7ffe87de2c7444fd86e693e4",
+                   "bytes": 160004506},
+    # FETCH_SIZE 314,620.3 KiB x 2.0 + WRITE_SIZE 622,592.0 KiB x 1.0 per dispatch
+    "prolate256": {"sha256": "d35bd89596a0242ba1a0d47242e2dba8823d0abd7ffe87de2c7444fd86e693e4",
+                   "bytes": 1281876582},
+    # FETCH_SIZE 90,248.9 KiB x 2.0 + WRITE_SIZE 131,328.0 KiB x 1.0 per dispatch: the FP16 reads
+    # count 1.37x their algorithmic bytes (partial lines at the tile edges of the shifted streams)
+    "settling384": {"sha256": "d35bd89596a0242ba1a0d47242e2dba8823d0abd7ffe87de2c7444fd86e693e4",
+                    "bytes": 319309619},
 }
 
 
@@ -79,26 +90,114 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(job, target_s: float = 15.0) -> dict:
-    """The FP64 oracle (as it stands) on the same workload, timed on the host's cores."""
+def host_info() -> dict:
+    """CPU model and the cores this process may run on (the GPU machine's share may be smaller
+    than what the kernel reports)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": nproc, "os_cpu_count": os.cpu_count()}
+
+
+def oracle_mlups(job, threads: int, target_s: float) -> dict:
+    """The FP64 oracle (as it stands) stepping job on `threads` host threads for about
+    target_s seconds after one untimed step (thread start-up, first touch)."""
     import oracle
-    cores = max(1, min(16, os.cpu_count() or 1))
-    oracle.set_threads(cores)
+    oracle.set_threads(threads)
     lat = oracle.Lattice(job.lattice)
-    lat.add_body(job.body, job.xyz, job.tri)
-    lat.step(1)   # thread start-up and first touch, untimed
+    if job.body is not None:
+        lat.add_body(job.body, job.xyz, job.tri)
+    lat.step(1)
     t0 = time.perf_counter()
-    lat.step(2)
-    one = (time.perf_counter() - t0) / 2.0
+    lat.step(1)
+    one = time.perf_counter() - t0
     n = max(1, min(5000, int(target_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     lat.step(n)
     dt = time.perf_counter() - t0
-    mlups = job.lattice.n * n / dt / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{n} full steps (IB + collide/stream + membrane) of the same "
-                      f"{job.lattice.nx}x{job.lattice.ny}x{job.lattice.nz} case after 3 steps, "
-                      f"{dt:.1f} s, FP64, OpenMP over lattice nodes"}
+    return {"value": round(job.lattice.n * n / dt / 1e6, 3), "threads": threads, "steps": n,
+            "seconds": round(dt, 2)}
+
+
+def cpu_baseline(job, target_s: float = 10.0, others=()) -> dict:
+    """The oracle on the headline workload on all the cores this process may use (at most 16,
+    the machine's CPU share for one GPU) and on one thread; `others` (name, job) pairs are timed the
+    same way, more briefly."""
+    host = host_info()
+    cores = max(1, min(16, host["nproc"]))
+    allc = oracle_mlups(job, cores, target_s)
+    one = oracle_mlups(job, 1, target_s)
+    lat = job.lattice
+    out = {"value": allc["value"], "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"{allc['steps']} full steps (IB + collide/stream + membrane) of the same "
+                     f"{lat.nx}x{lat.ny}x{lat.nz} case after 2 steps, {allc['seconds']} s, FP64, "
+                     f"OpenMP over lattice nodes on {cores} threads",
+           "single_thread": {"value": one["value"], "unit": "MLUPS", "cores": 1,
+                             "sample": f"{one['steps']} steps, {one['seconds']} s"},
+           "host": host}
+    extra = {}
+    for name, j in others:
+        a = oracle_mlups(j, cores, target_s / 2)
+        b = oracle_mlups(j, 1, target_s / 2)
+        extra[name] = {"all_cores_mlups": a["value"], "single_thread_mlups": b["value"],
+                       "steps": [a["steps"], b["steps"]]}
+    if extra:
+        out["other_workloads"] = extra
+    return out
+
+
+def run_plain(api, I, torch, name: str, seed: int, steps: int, warmup: int):
+    """The plain per-job form of one workload: timed steps with sampled sweep events."""
+    stream = torch.cuda.current_stream()
+    gen, gen_args, wl_text = WORKLOADS[name]
+    job = getattr(I, gen)(*gen_args) if gen_args is not None else getattr(I, gen)(seed)
+    spec = job.lattice
+    s_bytes = 4 if spec.storage == I.STORE_F32 else 2
+    lat = api.Lattice(spec, stream=stream)
+    lat.add_body(job.body, job.xyz, job.tri)
+    lat.step(warmup)
+    lat.sync()
+    lat.set_timing(TIMING_PERIOD)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat.sync()  # raises on instability / domain errors
+    sweep_ms, nsweep = lat.kernel_time(0)
+    step_ms, nstep = lat.kernel_time(1)
+    lat.set_timing(False)
+    lat.destroy()
+    n = spec.n
+    sweep_avg_s = sweep_ms / nsweep / 1e3
+    bytes_per_launch = 2 * 19 * s_bytes * n  # algorithmic: read and write 19 stored values per node
+    achieved = bytes_per_launch / sweep_avg_s / 1e9
+    roof_mlups = PEAK_HBM_GBS * 1e9 / (2 * 19 * s_bytes) / 1e6
+    mlups = n * steps / wall / 1e6
+    return dict(job=job, spec=spec, s_bytes=s_bytes, wl_text=wl_text, gen_args=gen_args, wall=wall,
+                mlups=mlups, sweep_avg_s=sweep_avg_s, nsweep=nsweep, step_ms=step_ms, nstep=nstep,
+                bytes_per_launch=bytes_per_launch, achieved=achieved, roof_mlups=roof_mlups)
+
+
+def plain_summary(r, steps: int) -> dict:
+    n = r["spec"].n
+    return {"mlups": round(r["mlups"], 2), "ms_per_step": round(r["wall"] / steps * 1e3, 5),
+            "full_step_frac_of_roofline_mlups": round(r["mlups"] / r["roof_mlups"], 4),
+            "sweep_us_avg": round(r["sweep_avg_s"] * 1e6, 3),
+            "sweep_frac": round(r["achieved"] / PEAK_HBM_GBS, 4),
+            "sweep_achieved_GBs": round(r["achieved"], 1),
+            "populations_bytes": 2 * 19 * r["s_bytes"] * n,
+            "lattice": [r["spec"].nx, r["spec"].ny, r["spec"].nz], "steps": steps}
 
 
 def calibrate_copy(nbytes: int, reps: int) -> None:
@@ -123,7 +222,8 @@ def calibrate_copy(nbytes: int, reps: int) -> None:
 
 def bench_batch(args) -> dict:
     """64 capsule-in-shear jobs in shared launches (FP16 shifted storage, hipGraph, autotuned
-    sweep shape) against the plain form: the same jobs one at a time with FP32 storage."""
+    sweep shape) against the plain form: the same jobs one at a time with FP32 storage, each
+    timed over a tenth of the batched steps (at least 10)."""
     import torch
     from paper_2207_06029_amd import api
     from paper_2207_06029_amd import inputs as I
@@ -166,9 +266,11 @@ def bench_batch(args) -> dict:
         lat.sync()
         lat.destroy()
     steps_job = jobs[0].steps
+    roof_mlups = PEAK_HBM_GBS * 1e9 / (2 * 19 * 2) / 1e6
     return {
         "metric": METRIC, "mode": "batch",
         "value": round(nodes / per_step / 1e6, 2), "unit": "MLUPS",
+        "full_step_frac_of_roofline_mlups": round(nodes / per_step / 1e6 / roof_mlups, 4),
         "jobs_per_hour": round(3600.0 / (per_step * steps_job) * len(jobs), 1),
         "plain_jobs_per_hour": round(3600.0 / (plain_s * steps_job) * len(jobs), 1) if plain_s else None,
         "plain_mlups": round(nodes / plain_s / 1e6, 2) if plain_s else None,
@@ -261,6 +363,8 @@ def make_parser() -> argparse.ArgumentParser:
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="plain mode: time only the chosen workload (no 256^3, settling and batch lines)")
     ap.add_argument("--calib-copy", type=int, default=0, help="bytes: run only a copy of that size")
     ap.add_argument("--graph", action="store_true",
                     help="also time the same steps replayed from a captured hipGraph")
@@ -301,31 +405,13 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    gen, gen_args, wl_text = WORKLOADS[args.workload]
-    job = getattr(I, gen)(*gen_args) if gen_args is not None else getattr(I, gen)(args.seed)
-    spec = job.lattice
-    s_bytes = 4 if spec.storage == I.STORE_F32 else 2
-    lat = api.Lattice(spec, stream=stream)
-    b = lat.add_body(job.body, job.xyz, job.tri)
-    lat.step(args.warmup)
-    lat.sync()
-
-    lat.set_timing(TIMING_PERIOD)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lat.step(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat.sync()  # raises on instability / domain errors
-    sweep_ms, nsweep = lat.kernel_time(0)
-    step_ms, nstep = lat.kernel_time(1)
-    lat.set_timing(False)
-
+    r = run_plain(api, I, torch, args.workload, args.seed, args.steps, args.warmup)
+    job, spec, s_bytes = r["job"], r["spec"], r["s_bytes"]
+    gen_args, wl_text = r["gen_args"], r["wl_text"]
     n = spec.n
-    mlups = n * args.steps / wall / 1e6
-    sweep_avg_s = sweep_ms / nsweep / 1e3
-    bytes_per_launch = 2 * 19 * s_bytes * n  # algorithmic: read and write 19 stored values per node
-    achieved = bytes_per_launch / sweep_avg_s / 1e9
+    sweep_avg_s, nsweep, step_ms, nstep = r["sweep_avg_s"], r["nsweep"], r["step_ms"], r["nstep"]
+    achieved, bytes_per_launch, wall = r["achieved"], r["bytes_per_launch"], r["wall"]
+    mlups = r["mlups"]
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -348,12 +434,16 @@ def main() -> int:
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload),
                      "kernel": "k_sweep<float,collide>" if s_bytes == 4 else "k_sweep<half,collide>",
                      "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": round(sweep_avg_s * 1e6, 3)},
+                     "avg_launch_us": round(sweep_avg_s * 1e6, 3),
+                     "working_set_bytes": bytes_per_launch,
+                     "infinity_cache_bytes": INFINITY_CACHE_BYTES,
+                     "cache_resident": bytes_per_launch <= INFINITY_CACHE_BYTES},
         "breakdown": {"sweep_us_avg": round(sweep_avg_s * 1e6, 3),
                       "sweep_launches_timed": nsweep,
                       "step_us_avg_events": round(step_ms / max(nstep, 1) * 1e3, 3),
                       "sweep_share_of_step": round(sweep_avg_s * 1e3 * nstep / max(step_ms, 1e-9), 4),
-                      "sweep_only_mlups": round(n / sweep_avg_s / 1e6, 1)},
+                      "sweep_only_mlups": round(n / sweep_avg_s / 1e6, 1),
+                      "full_step_frac_of_roofline_mlups": round(mlups / r["roof_mlups"], 4)},
     }
     if args.graph:
         # same job as a one-job batch whose steps replay a captured two-step hipGraph
@@ -368,8 +458,29 @@ def main() -> int:
         bt.sync()
         out["breakdown"]["graph_ms_per_step"] = round(gw / args.steps * 1e3, 5)
         out["breakdown"]["graph_mlups"] = round(n * args.steps / gw / 1e6, 2)
+    if not args.no_extras and args.workload == "prolate128":
+        # the other measured forms of the metric, each with its own fraction of the roofline:
+        # the FP32 case beyond the Infinity Cache, the FP16 rigid settling box, and the 64-job
+        # batch against the same jobs one at a time
+        xs = max(args.steps, EXTRA_MIN_STEPS)
+        xw = max(args.warmup, EXTRA_MIN_WARMUP)
+        extras = {}
+        for name in ("prolate256", "settling384"):
+            print(f"[bench] extra workload {name}: {xs} steps", file=sys.stderr, flush=True)
+            extras[name] = plain_summary(run_plain(api, I, torch, name, args.seed, xs, xw), xs)
+        print(f"[bench] extra workload batch64: {xs} steps", file=sys.stderr, flush=True)
+        bargs = argparse.Namespace(**{**vars(args), "steps": xs, "warmup": xw})
+        bt = bench_batch(bargs)
+        extras["batch64"] = {k: bt[k] for k in ("value", "unit", "full_step_frac_of_roofline_mlups",
+                                                  "jobs_per_hour", "plain_jobs_per_hour", "plain_mlups",
+                                                  "ms_per_batched_step", "launch_shape")}
+        extras["batch64"]["sweep_frac"] = bt["roofline"]["frac"]
+        extras["batch64"]["steps"] = xs
+        out["extra"] = extras
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(job)
+        others = () if args.no_extras else (("capsule32", I.capsule_shear_small()),
+                                              ("settling384", I.settling_sphere(1.5)))
+        out["cpu_baseline"] = cpu_baseline(job, others=others)
     print(json.dumps(out))
     return 0
 
