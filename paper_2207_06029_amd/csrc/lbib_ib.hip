@@ -1,10 +1,12 @@
 // Immersed-boundary and structure kernels (Secs. 1.2-1.3).
 //
-// One MLS point (triangle centroid, probe or vertex) is evaluated by a group of 16 lanes (one
-// DPP row); lane k owns nodes k and k + 16 of the 3x3x3 block around the nearest node.  Every
-// node within r_w of the point lies in that block, so the group covers the whole support of
-// Eq. (intKernel).  The 4x4 moment matrix is accumulated and factorised in FP64 (every lane
-// solves redundantly), so no lane waits on another except for the row butterfly sums.
+// One MLS point (triangle centroid, probe or vertex) is evaluated by a group of 8 lanes (half a
+// DPP row); lane k owns nodes k, k + 8, k + 16 and k + 24 of the 3x3x3 block around the nearest
+// node.  Every node within r_w of the point lies in that block, so the group covers the whole
+// support of Eq. (intKernel).  The 4x4 moment matrix is accumulated and factorised in FP64 (every
+// lane of the group solves redundantly), so no lane waits on another except for the butterfly
+// sums.  The marker kernels run one-wave blocks of eight points: few lanes per point keep the
+// instructions per point low, which bounds the batched launches.
 //
 // Step order inside the time step n -> n+1:
 //   k_centroids  triangle blocks: force window of this step from the vertex bounding box,
@@ -25,41 +27,64 @@
 
 namespace lbib {
 
-// Sum over the 16 lanes of an MLS group (one DPP row).  Lane exchanges xor 1 and xor 2 are
-// quad permutes, then row half-mirror and row mirror pair the 4- and 8-lane halves (after the
-// previous levels every lane of a block holds the same partial, so a mirror acts as an
-// exchange).  Each level adds the same two operands on both partners, so every lane ends with
-// the identical sum, and no value leaves the row.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
+// Sum over a group of G = 8 (half a DPP row) or 16 lanes (a row).  Lane exchanges xor 1 and xor 2
+// are quad permutes, then the row half-mirror pairs the two quads of 8 lanes and the row mirror
+// the two halves of a row (after the previous levels every lane of a block holds the same
+// partial, so a mirror acts as an exchange).  Each level adds the same two operands on both
+// partners, so every lane ends with the identical sum, and no value leaves the group.
+template <int G>
 __device__ __forceinline__ double gsum(double v) {
+    static_assert(G == 8 || G == 16, "groups of 8 or 16 lanes");
     v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
     v += dpp_f64<0x141>(v);  // row_half_mirror
-    v += dpp_f64<0x140>(v);  // row_mirror
+    if (G == 16) v += dpp_f64<0x140>(v);  // row_mirror
+    return v;
+}
+
+// Minimum / maximum over the wave: DPP within rows (quad permutes, half-mirror, mirror), then
+// two lane exchanges across rows.  Every lane ends with the result.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <bool MAX>
+__device__ __forceinline__ int wave_minmax(int v) {
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, dpp_i32<0xB1>(v));
+    v = op(v, dpp_i32<0x4E>(v));
+    v = op(v, dpp_i32<0x141>(v));
+    v = op(v, dpp_i32<0x140>(v));
+    v = op(v, __shfl_xor(v, 16, 64));
+    v = op(v, __shfl_xor(v, 32, 64));
     return v;
 }
 
 
-// One MLS point, per lane of its 16-lane group: lane k owns nodes k and k + 16 (when < 27) of
-// the 3x3x3 block around the nearest node.  mls_setup finds each node, its offset d = x_k - x,
+// One MLS point, per lane of its G-lane group: lane k owns nodes k + G s (when < 27) of the
+// 3x3x3 block around the nearest node.  mls_setup finds each node, its offset d = x_k - x,
 // |d|^2 and whether it supports the point (|d| <= r_w); the caller then issues its field loads,
 // and mls_solve builds and solves the moment system while those loads are in flight.
-constexpr int MLS_NODES = 2;   // stencil nodes per lane
+template <int G>
 struct MlsLane {
-    bool active[MLS_NODES];
-    int gx[MLS_NODES], gy[MLS_NODES], gz[MLS_NODES];
-    double d0[MLS_NODES], d1[MLS_NODES], d2[MLS_NODES], r2[MLS_NODES];
-    double phi[MLS_NODES];
-    double gr[MLS_NODES][3];
+    static constexpr int N = (27 + G - 1) / G;   // stencil nodes per lane
+    bool active[N];
+    int gx[N], gy[N], gz[N];
+    double d0[N], d1[N], d2[N], r2[N];
+    double phi[N];
+    double gr[N][3];
 };
 
+template <int G>
 __device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], double rw2, int lane,
-                                          MlsLane& m, int& err) {
+                                          MlsLane<G>& m, int& err) {
+    constexpr int MLS_NODES = MlsLane<G>::N;
     const int c0 = (int)floor(xp[0] + 0.5), c1 = (int)floor(xp[1] + 0.5), c2 = (int)floor(xp[2] + 0.5);
     const int dims[3] = {J.nx, J.ny, J.nz};
     // the nearest node wrapped once per periodic axis; its neighbours then wrap by +-n
@@ -71,7 +96,7 @@ __device__ __forceinline__ void mls_setup(const JobDev& J, const double xp[3], d
         }
 #pragma unroll
     for (int s = 0; s < MLS_NODES; ++s) {
-        const int k = lane + GROUP * s;
+        const int k = lane + G * s;
         m.active[s] = false;
         m.d0[s] = m.d1[s] = m.d2[s] = 0.0;
         m.r2[s] = 4.0 * rw2;
@@ -114,7 +139,9 @@ __device__ __forceinline__ double rcp64(double x) {
 // p = (1, d), W = exp(-(|d| / (r_w alpha))^2) (Eqs. l2norm, intKernel).  The weights are
 // evaluated in FP32; the moment matrix is accumulated and factorised (A = L D L^T, unit L) in
 // FP64 on every lane.
-__device__ __forceinline__ void mls_solve(MlsLane& m, float wq, bool want_grad, int& err) {
+template <int G>
+__device__ __forceinline__ void mls_solve(MlsLane<G>& m, float wq, bool want_grad, int& err) {
+    constexpr int MLS_NODES = MlsLane<G>::N;
     double W[MLS_NODES];
     double s00 = 0, s01 = 0, s02 = 0, s03 = 0, s11 = 0, s12 = 0, s13 = 0, s22 = 0, s23 = 0, s33 = 0;
 #pragma unroll
@@ -125,9 +152,9 @@ __device__ __forceinline__ void mls_solve(MlsLane& m, float wq, bool want_grad, 
         s11 += w * d0 * d0; s12 += w * d0 * d1; s13 += w * d0 * d2;
         s22 += w * d1 * d1; s23 += w * d1 * d2; s33 += w * d2 * d2;
     }
-    const double a00 = gsum(s00), a01 = gsum(s01), a02 = gsum(s02), a03 = gsum(s03);
-    const double a11 = gsum(s11), a12 = gsum(s12), a13 = gsum(s13);
-    const double a22 = gsum(s22), a23 = gsum(s23), a33 = gsum(s33);
+    const double a00 = gsum<G>(s00), a01 = gsum<G>(s01), a02 = gsum<G>(s02), a03 = gsum<G>(s03);
+    const double a11 = gsum<G>(s11), a12 = gsum<G>(s12), a13 = gsum<G>(s13);
+    const double a22 = gsum<G>(s22), a23 = gsum<G>(s23), a33 = gsum<G>(s33);
     // A = L D L^T
     const double e0 = a00;
     if (!(e0 > 0.0)) err |= FLAG_NONFINITE;
@@ -177,8 +204,10 @@ __device__ __forceinline__ long long win_index(const JobDev& J, const WinDesc& d
 
 // Moments (rho - 1, u*) of the lane's active stencil nodes from the body's moment window.
 // md: the layout of the moment window, which callers load with their other early reads
+template <int G>
 __device__ __forceinline__ void mls_moments(const Pools& P, const JobDev& J, const BodyDev& B, const WinDesc& md,
-                                            const MlsLane& m, float4 mom[MLS_NODES], int& err) {
+                                            const MlsLane<G>& m, float4 mom[MlsLane<G>::N], int& err) {
+    constexpr int MLS_NODES = MlsLane<G>::N;
 #pragma unroll
     for (int s = 0; s < MLS_NODES; ++s) {
         mom[s] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -191,15 +220,17 @@ __device__ __forceinline__ void mls_moments(const Pools& P, const JobDev& J, con
 
 // sum_k c_k q_k over the group for per-node coefficients c (phi or a gradient row) and field
 // values q (component `comp` of the moments: 0 rho - 1, 1..3 u*)
-__device__ __forceinline__ double group_dot(const double* c, int cstride, const float4 mom[MLS_NODES],
+template <int G>
+__device__ __forceinline__ double group_dot(const double* c, int cstride, const float4 mom[MlsLane<G>::N],
                                             int comp) {
+    constexpr int MLS_NODES = MlsLane<G>::N;
     double acc = 0.0;
 #pragma unroll
     for (int s = 0; s < MLS_NODES; ++s) {
         const float q = comp == 0 ? mom[s].x : (comp == 1 ? mom[s].y : (comp == 2 ? mom[s].z : mom[s].w));
         acc += c[s * cstride] * (double)q;
     }
-    return gsum(acc);
+    return gsum<G>(acc);
 }
 
 __device__ __forceinline__ void load3(const double* p, double v[3]) { v[0] = p[0]; v[1] = p[1]; v[2] = p[2]; }
@@ -341,8 +372,8 @@ __device__ __forceinline__ long long fix_rn(double v) {
 }
 
 // ---------------------------------------------------------------- spreading
-// The 16 markers of a block are neighbours on the mesh, so their stencils overlap: about 9
-// active nodes per marker, but only about 1.7 distinct nodes per marker over the block.  The
+// The markers of a block are neighbours on the mesh, so their stencils overlap: about 9 active
+// nodes per marker, but far fewer distinct nodes per marker over the block.  The
 // block therefore sums its contributions in LDS first (int64, so the order cannot change the
 // sum) and sends one global atomic per distinct node and component.  The LDS box is the
 // bounding box of the block's 3x3x3 stencils in unwrapped node coordinates; a block whose box
@@ -351,67 +382,45 @@ __device__ __forceinline__ long long fix_rn(double v) {
 // With fold set, the same block-wide reduction also folds the integer boxes that the vertex
 // blocks wrote for x^n into this step's force window (min / max, order independent): every
 // block derives the same descriptor and block 0 publishes it for the sweep and the moments.
-// vb[6] is this thread's vertex-block box (first entry; further ones are folded here).
+// vb[6] is the box of the vertex-block boxes this thread loaded.
 // Without fold, fd_in is the window the window kernel of the previous step published.
-constexpr int SPREAD_LDS_NODES = 512;
+constexpr int SPREAD_LDS_NODES = 256;
 
+template <int G>
 __device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, const BodyDev& B, int b,
                                              int blk, bool fold, const int vb[6], const WinDesc& fd_in,
-                                             bool live, const int cen_node[3], const MlsLane& m,
-                                             int lane, const long long fx[MLS_NODES][3], int& err) {
+                                             bool live, const int cen_node[3], const MlsLane<G>& m,
+                                             int lane, const long long fx[MlsLane<G>::N][3], int& err) {
+    constexpr int MLS_NODES = MlsLane<G>::N;
+    static_assert(IB_BLOCK == 64, "the block is one wave: its boxes are wave reductions");
     __shared__ long long s_acc[3][SPREAD_LDS_NODES];
-    __shared__ int s_box[4][12];
     const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
     unsigned long long* fw0 = (unsigned long long*)(P.fwin + 3 * B.win_off);
-    // r[0..2] / r[3..5]: stencil box of the live markers; r[6..8] / r[9..11]: vertex boxes
-    int r[12];
-    for (int a = 0; a < 3; ++a) {
-        r[a] = live ? cen_node[a] - 1 : 0x3fffffff;
-        r[3 + a] = live ? cen_node[a] + 1 : -0x3fffffff;
-        r[6 + a] = vb[a];
-        r[9 + a] = vb[3 + a];
-    }
-    if (fold)
-        for (int q = threadIdx.x + blockDim.x; q < B.nblk_v; q += blockDim.x) {
-            const int* e = P.vbox + 6LL * (B.blk_v0 + q);
-            for (int a = 0; a < 3; ++a) { r[6 + a] = min(r[6 + a], e[a]); r[9 + a] = max(r[9 + a], e[3 + a]); }
-        }
-    for (int sh = 32; sh >= 1; sh >>= 1)
-        for (int a = 0; a < 3; ++a) {
-            r[a] = min(r[a], __shfl_xor(r[a], sh, 64));
-            r[3 + a] = max(r[3 + a], __shfl_xor(r[3 + a], sh, 64));
-            if (fold) {
-                r[6 + a] = min(r[6 + a], __shfl_xor(r[6 + a], sh, 64));
-                r[9 + a] = max(r[9 + a], __shfl_xor(r[9 + a], sh, 64));
-            }
-        }
-    const int wave = threadIdx.x / 64;
-    if ((threadIdx.x & 63) == 0)
-        for (int i = 0; i < 12; ++i) s_box[wave][i] = r[i];
-    for (int i = threadIdx.x; i < 3 * SPREAD_LDS_NODES; i += blockDim.x) (&s_acc[0][0])[i] = 0;
-    __syncthreads();
+    // stencil box of the live markers; with fold, the box of the vertex-block boxes
     int o[3], w[3], bmin[3], bmax[3];
-    long long vol = 1;
+    bool small = true;   // every side within the LDS box (also keeps the volume from overflowing)
     for (int a = 0; a < 3; ++a) {
-        int l = s_box[0][a], h = s_box[0][3 + a];
-        bmin[a] = s_box[0][6 + a];
-        bmax[a] = s_box[0][9 + a];
-        for (int q = 1; q < 4; ++q) {
-            l = min(l, s_box[q][a]);
-            h = max(h, s_box[q][3 + a]);
-            bmin[a] = min(bmin[a], s_box[q][6 + a]);
-            bmax[a] = max(bmax[a], s_box[q][9 + a]);
-        }
+        const int l = wave_minmax<false>(live ? cen_node[a] - 1 : 0x3fffffff);
+        const int h = wave_minmax<true>(live ? cen_node[a] + 1 : -0x3fffffff);
         o[a] = l;
         w[a] = h >= l ? h - l + 1 : 1;
-        vol *= w[a];
+        small = small && w[a] <= SPREAD_LDS_NODES;
+        if (fold) {
+            bmin[a] = wave_minmax<false>(vb[a]);
+            bmax[a] = wave_minmax<true>(vb[3 + a]);
+        }
     }
     WinDesc fd = fd_in;
     if (fold) {
         fd = window_from_box(J, B, bmin, bmax, err);
         if (blk == 0 && threadIdx.x == 0) P.fdesc[b] = fd;
     }
+    const int vol = small ? w[0] * w[1] * w[2] : SPREAD_LDS_NODES + 1;
     const bool use_lds = vol <= SPREAD_LDS_NODES;   // uniform over the block
+    if (use_lds) {
+        for (int i = threadIdx.x; i < vol; i += blockDim.x) s_acc[0][i] = s_acc[1][i] = s_acc[2][i] = 0;
+        __syncthreads();
+    }
     if (live) {
 #pragma unroll
         for (int sn = 0; sn < MLS_NODES; ++sn) {
@@ -422,7 +431,7 @@ __device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, co
                 continue;
             }
             if (use_lds) {
-                const int k = lane + GROUP * sn;
+                const int k = lane + G * sn;
                 const int li = (cen_node[0] + k % 3 - 1 - o[0]) +
                                w[0] * ((cen_node[1] + (k / 3) % 3 - 1 - o[1]) + w[1] * (cen_node[2] + k / 9 - 1 - o[2]));
                 for (int c = 0; c < 3; ++c)
@@ -436,7 +445,7 @@ __device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, co
     if (!use_lds) return;
     __syncthreads();
     const int dims[3] = {J.nx, J.ny, J.nz};
-    for (int i = threadIdx.x; i < (int)vol; i += blockDim.x) {
+    for (int i = threadIdx.x; i < vol; i += blockDim.x) {
         const long long v0 = s_acc[0][i], v1 = s_acc[1][i], v2 = s_acc[2][i];
         if (!(v0 | v1 | v2)) continue;
         // back to wrapped lattice coordinates; only nodes with a window index received sums
@@ -456,14 +465,15 @@ __device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, co
 }
 
 // ---------------------------------------------------------------- centroids (+ hinges)
-template <bool SOLO>
-__global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fold) {
+template <bool SOLO, int G>
+__global__ void __launch_bounds__(IB_BLOCK) k_centroids(Pools P, int nblk_tri, int fold) {
+    constexpr int MLS_NODES = MlsLane<G>::N, MLS_PER_BLOCK = IB_BLOCK / G;
     if ((int)blockIdx.x >= nblk_tri) {
         // edge blocks: one thread per hinge of a membrane
         const int eb = blockIdx.x - nblk_tri;
         const int b = block_body<SOLO>(P, P.blk_body_e, eb);
         const BodyDev& B = body_of<SOLO>(P, b);
-        const int e = (eb - B.blk_e0) * 256 + threadIdx.x;
+        const int e = (eb - B.blk_e0) * IB_BLOCK + threadIdx.x;
         if (e >= B.ne) return;
         double f[15];
         hinge_forces(P, B, e, f);
@@ -475,7 +485,7 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
     const BodyDev& B = body_of<SOLO>(P, b);
     const JobDev& J = body_job<SOLO>(P, B);
     BodyState& S = P.bstate[b];
-    const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int blk = blockIdx.x - B.blk_c0;
     const int t = blk * MLS_PER_BLOCK + grp;
     const bool live = t < B.nt;
@@ -488,9 +498,10 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
     WinDesc fd_pub = {};
     const WinDesc md = P.mdesc[b];
     if (fold) {
-        if ((int)threadIdx.x < B.nblk_v) {
-            const int* e = P.vbox + 6LL * (B.blk_v0 + threadIdx.x);
-            for (int i = 0; i < 6; ++i) vb[i] = e[i];
+        // every vertex-block box, loaded now so that these loads overlap the MLS work
+        for (int q = threadIdx.x; q < B.nblk_v; q += blockDim.x) {
+            const int* e = P.vbox + 6LL * (B.blk_v0 + q);
+            for (int a = 0; a < 3; ++a) { vb[a] = min(vb[a], e[a]); vb[3 + a] = max(vb[3 + a], e[3 + a]); }
         }
     } else {
         fd_pub = P.fdesc[b];
@@ -509,7 +520,7 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
     double Vt = 0.0;
     int cen_node[3] = {0, 0, 0};               // node nearest to the centroid (unwrapped)
     long long fx[MLS_NODES][3] = {};           // fixed-point force of each stencil node
-    MlsLane m;
+    MlsLane<G> m;
     if (live) {
         double cen[3], ab[3], ac[3], N[3];
         for (int a = 0; a < 3; ++a) {
@@ -532,14 +543,14 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
             cross3(pb, pc, bc);
             Vt = dot3(pa, bc) * (1.0 / 6.0);
         }
-        mls_setup(J, cen, B.rw2, lane, m, err);
+        mls_setup<G>(J, cen, B.rw2, lane, m, err);
         for (int a = 0; a < 3; ++a) cen_node[a] = (int)floor(cen[a] + 0.5);
         float4 mom[MLS_NODES];
-        mls_moments(P, J, B, md, m, mom, err);
-        mls_solve(m, B.wq, false, err);
-        const double U0 = group_dot(m.phi, 1, mom, 1);
-        const double U1 = group_dot(m.phi, 1, mom, 2);
-        const double U2 = group_dot(m.phi, 1, mom, 3);
+        mls_moments<G>(P, J, B, md, m, mom, err);
+        mls_solve<G>(m, B.wq, false, err);
+        const double U0 = group_dot<G>(m.phi, 1, mom, 1);
+        const double U1 = group_dot<G>(m.phi, 1, mom, 2);
+        const double U2 = group_dot<G>(m.phi, 1, mom, 3);
         // desired boundary velocity U_b (Sec. 1.2): membranes average their vertex velocities,
         // rigid bodies move the marker with the body
         if (B.rigid) {
@@ -557,7 +568,7 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
             fx[sn][2] = fix_rn(sc * (Ub[2] - U2) * FIX_SCALE);
         }
     }
-    spread_block(P, J, B, b, blk, fold != 0, vb, fd_pub, live, cen_node, m, lane, fx, err);
+    spread_block<G>(P, J, B, b, blk, fold != 0, vb, fd_pub, live, cen_node, m, lane, fx, err);
     if (err) atomicOr(P.flags + B.job, err);
     if (B.rigid || B.kv == 0.0) return;
     if (lane == 0) vol[grp] = Vt;
@@ -571,27 +582,28 @@ __global__ void __launch_bounds__(256) k_centroids(Pools P, int nblk_tri, int fo
 // Fluid velocity at every membrane vertex from the moments of f^{n+1} (the tentative velocity
 // of Eq. verletPos).  It needs nothing from the probes, so its blocks ride in the probe launch
 // and the vertex kernel only gathers forces and moves the vertices.  One group per vertex.
-template <bool SOLO>
+template <bool SOLO, int G>
 __device__ void vertex_velocity_block(const Pools& P, int vb) {
-    const int b = block_body<SOLO>(P, P.blk_body_v, vb);
+    constexpr int MLS_NODES = MlsLane<G>::N, MLS_PER_BLOCK = IB_BLOCK / G;
+    const int b = block_body<SOLO>(P, P.blk_body_u, vb);
     const BodyDev& B = body_of<SOLO>(P, b);
     if (B.rigid) return;
     const JobDev& J = body_job<SOLO>(P, B);
-    const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
-    const int v = (vb - B.blk_v0) * MLS_PER_BLOCK + grp;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int v = (vb - B.blk_u0) * MLS_PER_BLOCK + grp;
     if (v >= B.nv) return;
     const long long gv = B.v0 + v;
     int err = 0;
     double x[3];
     load3(P.x + 3 * gv, x);
     const WinDesc md = P.mdesc[b];
-    MlsLane m;
+    MlsLane<G> m;
     float4 mom[MLS_NODES];
-    mls_setup(J, x, B.rw2, lane, m, err);
-    mls_moments(P, J, B, md, m, mom, err);
-    mls_solve(m, B.wq, false, err);
-    const double u0 = group_dot(m.phi, 1, mom, 1), u1 = group_dot(m.phi, 1, mom, 2),
-                 u2 = group_dot(m.phi, 1, mom, 3);
+    mls_setup<G>(J, x, B.rw2, lane, m, err);
+    mls_moments<G>(P, J, B, md, m, mom, err);
+    mls_solve<G>(m, B.wq, false, err);
+    const double u0 = group_dot<G>(m.phi, 1, mom, 1), u1 = group_dot<G>(m.phi, 1, mom, 2),
+                 u2 = group_dot<G>(m.phi, 1, mom, 3);
     if (lane == 0) {
         P.u0v[3 * gv] = u0;
         P.u0v[3 * gv + 1] = u1;
@@ -603,17 +615,18 @@ __device__ void vertex_velocity_block(const Pools& P, int vb) {
 // ---------------------------------------------------------------- triangles (probes)
 // Group 2k evaluates the outer probe of triangle k of the block, group 2k+1 the inner one.
 // Blocks from nblk_tri on compute the vertex velocities instead.
-template <bool SOLO>
-__global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
+template <bool SOLO, int G>
+__global__ void __launch_bounds__(IB_BLOCK) k_triangles(Pools P, int nblk_tri) {
+    constexpr int MLS_NODES = MlsLane<G>::N, MLS_PER_BLOCK = IB_BLOCK / G, TRI_PER_BLOCK = MLS_PER_BLOCK / 2;
     if ((int)blockIdx.x >= nblk_tri) {
-        vertex_velocity_block<SOLO>(P, blockIdx.x - nblk_tri);
+        vertex_velocity_block<SOLO, G>(P, blockIdx.x - nblk_tri);
         return;
     }
     const int b = block_body<SOLO>(P, P.blk_body_t, blockIdx.x);
     const BodyDev& B = body_of<SOLO>(P, b);
     const JobDev& J = body_job<SOLO>(P, B);
     BodyState& S = P.bstate[b];
-    const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int blk = blockIdx.x - B.blk_t0;
     const int k = grp >> 1, side = grp & 1;
     const int t = blk * TRI_PER_BLOCK + k;
@@ -632,18 +645,18 @@ __global__ void __launch_bounds__(256) k_triangles(Pools P, int nblk_tri) {
         const double sg = side == 0 ? 1.0 : -1.0;
         const double xp[3] = {cen[0] + sg * B.probe * nrm[0], cen[1] + sg * B.probe * nrm[1],
                               cen[2] + sg * B.probe * nrm[2]};
-        MlsLane m;
-        mls_setup(J, xp, B.rw2, lane, m, err);
+        MlsLane<G> m;
+        mls_setup<G>(J, xp, B.rw2, lane, m, err);
         float4 mom[MLS_NODES];
-        mls_moments(P, J, B, md, m, mom, err);
-        mls_solve(m, B.wq, true, err);
+        mls_moments<G>(P, J, B, md, m, mom, err);
+        mls_solve<G>(m, B.wq, true, err);
         // interpolated rho - 1 and the gradient rows of u* (diffuse derivatives)
         double v[10];
-        v[0] = group_dot(m.phi, 1, mom, 0);
+        v[0] = group_dot<G>(m.phi, 1, mom, 0);
         for (int j = 0; j < 3; ++j) {
-            v[1 + j] = group_dot(&m.gr[0][j], 3, mom, 1);
-            v[4 + j] = group_dot(&m.gr[0][j], 3, mom, 2);
-            v[7 + j] = group_dot(&m.gr[0][j], 3, mom, 3);
+            v[1 + j] = group_dot<G>(&m.gr[0][j], 3, mom, 1);
+            v[4 + j] = group_dot<G>(&m.gr[0][j], 3, mom, 2);
+            v[7 + j] = group_dot<G>(&m.gr[0][j], 3, mom, 3);
         }
         if (lane == 0)
             for (int i = 0; i < 10; ++i) probe[grp][i] = v[i];
@@ -778,22 +791,22 @@ __device__ __forceinline__ int box_lo(double v) { return (int)floor(fmin(fmax(v,
 __device__ __forceinline__ int box_hi(double v) { return (int)ceil(fmin(fmax(v, -1e7), 1e7)); }
 
 template <bool SOLO>
-__global__ void __launch_bounds__(256) k_vertices(Pools P) {
+__global__ void __launch_bounds__(VERT_BLOCK) k_vertices(Pools P) {
     const int b = block_body<SOLO>(P, P.blk_body_v, blockIdx.x);
     const BodyDev& B = body_of<SOLO>(P, b);
     const JobDev& J = body_job<SOLO>(P, B);
     BodyState& S = P.bstate[b];
-    const int grp = threadIdx.x / GROUP, lane = threadIdx.x % GROUP;
+    const int grp = threadIdx.x / VERT_GROUP, lane = threadIdx.x % VERT_GROUP;
     const int blk = blockIdx.x - B.blk_v0;
-    const int v = blk * MLS_PER_BLOCK + grp;
-    __shared__ int box[MLS_PER_BLOCK][6];
+    const int v = blk * VERT_PER_BLOCK + grp;
+    __shared__ int box[VERT_PER_BLOCK][6];
     int err = 0;
     int bl[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, bh[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
     if (v < B.nv) {
         const long long gv = B.v0 + v;
         // incidence entries first (lane j holds entry j when the lists fit in a group), so
         // that the force loads they address go out together with the moment loads
-        const bool one = B.vt_w <= GROUP && B.vh_w <= GROUP;
+        const bool one = B.vt_w <= VERT_GROUP && B.vh_w <= VERT_GROUP;
         int tl0 = -1, hc0 = -1;
         if (one) {
             if (lane < B.vt_w) tl0 = P.vt_list[B.vt_off + (long long)v * B.vt_w + lane];
@@ -821,17 +834,17 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
             if (tl0 >= 0) add_tri(tl0);
             if (hc0 >= 0) add_hinge(hc0);
         } else {
-            for (int j = lane; j < B.vt_w; j += GROUP) {
+            for (int j = lane; j < B.vt_w; j += VERT_GROUP) {
                 const int tl = P.vt_list[B.vt_off + (long long)v * B.vt_w + j];
                 if (tl >= 0) add_tri(tl);
             }
             if (!B.rigid)
-                for (int j = lane; j < B.vh_w; j += GROUP) {
+                for (int j = lane; j < B.vh_w; j += VERT_GROUP) {
                     const int code = P.vh_list[B.vh_off + (long long)v * B.vh_w + j];
                     if (code >= 0) add_hinge(code);
                 }
         }
-        const double F0 = gsum(f[0]), F1 = gsum(f[1]), F2 = gsum(f[2]);
+        const double F0 = gsum<VERT_GROUP>(f[0]), F1 = gsum<VERT_GROUP>(f[1]), F2 = gsum<VERT_GROUP>(f[2]);
         if (!B.rigid) {
             // tentative velocity u0: fluid velocity at the vertex from f^{n+1}
             const double Fv[3] = {F0, F1, F2};
@@ -889,7 +902,7 @@ __global__ void __launch_bounds__(256) k_vertices(Pools P) {
         int* vb = P.vbox + 6LL * blockIdx.x;
         for (int a = 0; a < 3; ++a) {
             int lo = box[0][a], hi = box[0][3 + a];
-            for (int g = 1; g < MLS_PER_BLOCK; ++g) { lo = min(lo, box[g][a]); hi = max(hi, box[g][3 + a]); }
+            for (int g = 1; g < VERT_PER_BLOCK; ++g) { lo = min(lo, box[g][a]); hi = max(hi, box[g][3 + a]); }
             vb[a] = lo;
             vb[3 + a] = hi;
         }
@@ -968,8 +981,9 @@ __global__ void __launch_bounds__(256) k_body_totals(Pools P, int b, double* out
 
 void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, bool fold, hipStream_t s) {
     if (!(nblk_tri + nblk_edge > 0)) return;
-    if (P.solo_job >= 0) hipLaunchKernelGGL(k_centroids<true>, dim3(nblk_tri + nblk_edge), dim3(256), 0, s, P, nblk_tri, (int)fold);
-    else hipLaunchKernelGGL(k_centroids<false>, dim3(nblk_tri + nblk_edge), dim3(256), 0, s, P, nblk_tri, (int)fold);
+    const dim3 grid(nblk_tri + nblk_edge), block(IB_BLOCK);
+    if (P.solo_job >= 0) hipLaunchKernelGGL((k_centroids<true, MLS_GROUP>), grid, block, 0, s, P, nblk_tri, (int)fold);
+    else hipLaunchKernelGGL((k_centroids<false, MLS_GROUP>), grid, block, 0, s, P, nblk_tri, (int)fold);
 }
 void launch_windows(const Pools& P, int nbodies, hipStream_t s) {
     if (nbodies > 0) hipLaunchKernelGGL(k_windows, dim3(nbodies), dim3(256), 0, s, P);
@@ -978,15 +992,16 @@ void launch_fold_bodies(const Pools& P, int nbodies, int mode, hipStream_t s) {
     if (nbodies > 0) hipLaunchKernelGGL(k_fold_bodies, dim3(nbodies), dim3(256), 0, s, P, mode);
 }
 
-void launch_triangles(const Pools& P, int nblk_tri, int nblk_vert, hipStream_t s) {
-    if (!(nblk_tri + nblk_vert > 0)) return;
-    if (P.solo_job >= 0) hipLaunchKernelGGL(k_triangles<true>, dim3(nblk_tri + nblk_vert), dim3(256), 0, s, P, nblk_tri);
-    else hipLaunchKernelGGL(k_triangles<false>, dim3(nblk_tri + nblk_vert), dim3(256), 0, s, P, nblk_tri);
+void launch_triangles(const Pools& P, int nblk_tri, int nblk_vel, hipStream_t s) {
+    if (!(nblk_tri + nblk_vel > 0)) return;
+    const dim3 grid(nblk_tri + nblk_vel), block(IB_BLOCK);
+    if (P.solo_job >= 0) hipLaunchKernelGGL((k_triangles<true, MLS_GROUP>), grid, block, 0, s, P, nblk_tri);
+    else hipLaunchKernelGGL((k_triangles<false, MLS_GROUP>), grid, block, 0, s, P, nblk_tri);
 }
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s) {
     if (!(nblocks > 0)) return;
-    if (P.solo_job >= 0) hipLaunchKernelGGL(k_vertices<true>, dim3(nblocks), dim3(256), 0, s, P);
-    else hipLaunchKernelGGL(k_vertices<false>, dim3(nblocks), dim3(256), 0, s, P);
+    if (P.solo_job >= 0) hipLaunchKernelGGL(k_vertices<true>, dim3(nblocks), dim3(VERT_BLOCK), 0, s, P);
+    else hipLaunchKernelGGL(k_vertices<false>, dim3(nblocks), dim3(VERT_BLOCK), 0, s, P);
 }
 void launch_body_totals(const Pools& P, int body, double* out6, hipStream_t s) {
     hipLaunchKernelGGL(k_body_totals, dim3(1), dim3(256), 0, s, P, body, out6);

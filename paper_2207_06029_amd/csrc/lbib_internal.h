@@ -19,8 +19,17 @@ constexpr int Q = 19;
 constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
 constexpr double FIX_INV = 1.0 / 1099511627776.0;
 constexpr int WIN_MARGIN = 4;    // nodes around a body's bounding box (probe + support + slack)
-constexpr int GROUP = 16;         // lanes that evaluate one MLS point (one DPP row)
-constexpr int MLS_PER_BLOCK = 16; // MLS points (16-lane groups) per 256-thread block
+constexpr int IB_BLOCK = 64;      // threads per block of the marker kernels: one wave
+// lanes that evaluate one MLS point (four stencil nodes each), MLS points per block, and
+// triangles per probe block (two points, the +/- probes, per triangle)
+constexpr int MLS_GROUP = 8;
+constexpr int MLS_PER_BLOCK = IB_BLOCK / MLS_GROUP;
+constexpr int TRI_PER_BLOCK = MLS_PER_BLOCK / 2;
+// the vertex kernel gathers each vertex's incident forces with 16 lanes (one DPP row), 16
+// vertices per block (the centroid blocks fold one box per vertex block into the force window)
+constexpr int VERT_GROUP = 16;
+constexpr int VERT_BLOCK = 256;
+constexpr int VERT_PER_BLOCK = VERT_BLOCK / VERT_GROUP;
 constexpr int MAX_RED_BLOCKS = 65536;
 // window-moments blocks per body: one 256-thread block per this many nodes of window capacity
 constexpr int WIN_NODES_PER_BLOCK = 2048;
@@ -116,6 +125,7 @@ struct BodyDev {
     int vt_w, vh_w;
     // first block of this body in the centroid / edge / triangle / vertex grids, block counts
     int blk_c0, nblk_c, blk_e0, nblk_e, blk_t0, nblk_t, blk_v0, nblk_v, blk_w0, nblk_w;
+    int blk_u0, nblk_u;   // vertex-velocity blocks of the probe launch
     double kb, kv, mv, V0, mass;
     double rw, alpha, probe, shell_h;
     double rw2;                 // r_w^2: support test on squared distances
@@ -143,7 +153,8 @@ struct Pools {
     const int* blk_body_c;   // block -> body for the centroid kernel (triangle blocks)
     const int* blk_body_e;   // block -> body for the edge blocks of the centroid kernel
     const int* blk_body_t;
-    const int* blk_body_v;
+    const int* blk_body_v;   // block -> body for the vertex kernel
+    const int* blk_body_u;   // block -> body for the vertex-velocity blocks of the probe kernel
     const int* blk_body_w;   // block -> body for the window-moments kernel
     double* x;               // [3 nv] positions x^n (all bodies concatenated)
     double* xprev;           // [3 nv] x^{n-1}
@@ -239,11 +250,10 @@ void launch_centroids(const Pools& P, int nblk_tri, int nblk_edge, bool fold, hi
 void launch_windows(const Pools& P, int nbodies, hipStream_t s);
 // bodies from which the force windows are folded once per body by a kernel of their own
 constexpr int WINDOW_KERNEL_MIN_BODIES = 2;
-void launch_triangles(const Pools& P, int nblk_tri, int nblk_vert, hipStream_t s);
+void launch_triangles(const Pools& P, int nblk_tri, int nblk_vel, hipStream_t s);
 // mode 0: volumes of membranes with a volume penalty; mode 1: rigid totals and pose update
 void launch_fold_bodies(const Pools& P, int nbodies, int mode, hipStream_t s);
 void launch_vertices(const Pools& P, int nblocks, hipStream_t s);
 void launch_body_totals(const Pools& P, int body, double* out6, hipStream_t s);
-constexpr int TRI_PER_BLOCK = 8;  // probe kernel: two 16-lane groups (+/- probe) per triangle
 
 }  // namespace lbib

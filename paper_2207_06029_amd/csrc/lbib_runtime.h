@@ -70,7 +70,7 @@ struct Batch {
     std::vector<HostBody> hbodies;
     std::vector<BodyDev> host_bodies;
     int nbodies = 0;
-    int nblk_c = 0, nblk_e = 0, nblk_t = 0, nblk_v = 0, nblk_w = 0;
+    int nblk_c = 0, nblk_e = 0, nblk_t = 0, nblk_v = 0, nblk_u = 0, nblk_w = 0;
     bool any_rigid = false, any_volume = false;   // bodies needing the per-body fold launches
     Pools P{};
     bool cur_b = false;        // buffer holding the latest post-collision state

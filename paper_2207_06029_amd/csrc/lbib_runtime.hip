@@ -130,10 +130,11 @@ size_t workspace_need(const lbib_lattice_desc& d, long long nv, long long nt) {
     if (!body) nv = nt = 0;
     const long long ne = 3 * nt / 2;
     const long long nbc = (nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbt = (nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
-    const long long nbv = (nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbe = (ne + 255) / 256;
+    const long long nbu = (nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
+    const long long nbv = (nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK, nbe = (ne + IB_BLOCK - 1) / IB_BLOCK;
     const long long capn = body ? n : 0;
     const long long nbw = body ? std::max<long long>(1, (capn + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK) : 0;
-    b += r(sizeof(BodyDev)) + r(4 * nbc) + r(4 * nbe) + r(4 * nbt) + r(4 * nbv) + r(4 * nbw);
+    b += r(sizeof(BodyDev)) + r(4 * nbc) + r(4 * nbe) + r(4 * nbt) + r(4 * nbv) + r(4 * nbu) + r(4 * nbw);
     b += 6 * r(24 * nv);                                             // x, xprev, uv, fv, u0v, xb
     b += r(12 * nt) + r(8 * ne) + r(16 * ne) + 3 * r(8 * ne);        // tri, edge, hinge, l0, ks, theta0
     b += r(4 * nv * WS_MAX_VALENCE) + r(4 * nv * 2 * WS_MAX_VALENCE);  // incidence lists
@@ -482,13 +483,13 @@ lbib_status Batch::rebuild_bodies() {
     std::stable_sort(hbodies.begin(), hbodies.end(), [](const HostBody& a, const HostBody& b) { return a.job < b.job; });
     for (auto& J : jobs) { J.body0 = 0; J.nbodies = 0; }
     std::vector<BodyDev> bd(hbodies.size());
-    std::vector<int> bc, be, bt, bv, bw, vbox;
+    std::vector<int> bc, be, bt, bv, bu, bw, vbox;
     std::vector<double> x, xprev, uv, xb, l0, ks, th0;
     std::vector<int> tri, edge, hinge, vtl, vhl;
     std::vector<WinDesc> fd(hbodies.size());
     std::vector<BodyState> bs(hbodies.size());
     long long v0 = 0, t0 = 0, e0 = 0, woff = 0, red = 0;
-    nblk_c = nblk_e = nblk_t = nblk_v = nblk_w = 0;
+    nblk_c = nblk_e = nblk_t = nblk_v = nblk_u = nblk_w = 0;
     for (size_t i = 0; i < hbodies.size(); ++i) {
         HostBody& h = hbodies[i];
         JobDev& J = jobs[h.job];
@@ -532,12 +533,14 @@ lbib_status Batch::rebuild_bodies() {
         woff += capn;
         const int nbc = (h.nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
         const int nbt = (h.nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
-        const int nbv = (h.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
-        const int nbe = h.desc.rigid ? 0 : (h.ne + 255) / 256;
+        const int nbu = (h.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
+        const int nbv = (h.nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK;
+        const int nbe = h.desc.rigid ? 0 : (h.ne + IB_BLOCK - 1) / IB_BLOCK;
         B.blk_c0 = nblk_c; B.nblk_c = nbc; nblk_c += nbc;
         B.blk_e0 = nblk_e; B.nblk_e = nbe; nblk_e += nbe;
         B.blk_t0 = nblk_t; B.nblk_t = nbt; nblk_t += nbt;
         B.blk_v0 = nblk_v; B.nblk_v = nbv; nblk_v += nbv;
+        B.blk_u0 = nblk_u; B.nblk_u = nbu; nblk_u += nbu;
         const int nbw = (int)std::max<long long>(1, (capn + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
         B.blk_w0 = nblk_w; B.nblk_w = nbw; nblk_w += nbw;
         for (int k = 0; k < nbw; ++k) bw.push_back((int)i);
@@ -545,6 +548,7 @@ lbib_status Batch::rebuild_bodies() {
         for (int k = 0; k < nbe; ++k) be.push_back((int)i);
         for (int k = 0; k < nbt; ++k) bt.push_back((int)i);
         for (int k = 0; k < nbv; ++k) bv.push_back((int)i);
+        for (int k = 0; k < nbu; ++k) bu.push_back((int)i);
         B.red_slot = (int)red;
         red += std::max(nbc, nbt);
         x.insert(x.end(), h.x.begin(), h.x.end());
@@ -592,6 +596,7 @@ lbib_status Batch::rebuild_bodies() {
     if ((st = upload(arena, be, (int**)&P.blk_body_e, stream))) return st;
     if ((st = upload(arena, bt, (int**)&P.blk_body_t, stream))) return st;
     if ((st = upload(arena, bv, (int**)&P.blk_body_v, stream))) return st;
+    if ((st = upload(arena, bu, (int**)&P.blk_body_u, stream))) return st;
     if ((st = upload(arena, bw, (int**)&P.blk_body_w, stream))) return st;
     if ((st = upload(arena, x, &P.x, stream))) return st;
     if ((st = upload(arena, xprev, &P.xprev, stream))) return st;
@@ -810,7 +815,7 @@ lbib_status Batch::enqueue_step(bool collide) {
     cur_b = !cur_b;
     if (bodies) {
         launch_window_moments(P, storage, cur_b, nblk_w, stream);
-        launch_triangles(P, nblk_t, nblk_v, stream);
+        launch_triangles(P, nblk_t, nblk_u, stream);
         if (any_rigid) launch_fold_bodies(P, nbodies, 1, stream);
         launch_vertices(P, nblk_v, stream);
         if (fold_once) launch_windows(P, nbodies, stream);
