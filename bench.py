@@ -447,7 +447,7 @@ def main() -> int:
                       "full_step_frac_of_roofline_mlups": round(mlups / r["roof_mlups"], 4)},
     }
     if args.graph:
-        # same job as a one-job batch whose steps replay a captured two-step hipGraph
+        # same job as a one-job batch whose steps replay a captured hipGraph of 16 steps
         bt = api.Batch([job], storage=spec.storage, use_graph=True, stream=stream)
         bt.step(args.warmup)
         bt.sync()

@@ -246,10 +246,11 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
 // Deterministic per-body totals.  Every block of a body stores its partial sums (up to six
 // values, in a slot of 16 doubles); one block per body folds them in a later launch, whose
 // boundary makes the partials visible without a per-block device-scope release (each of which
-// would write back an L2).  Thread t takes blocks t, t+256, ... in order, then a fixed-shape
-// tree in LDS combines the 256 results: the order depends only on the body's own block count,
+// would write back an L2).  Thread t takes blocks t, t+512, ... in order, then a fixed-shape
+// tree in LDS combines the 512 results: the order depends only on the body's own block count,
 // so totals are bitwise reproducible and independent of other jobs in the launch.
 constexpr int FOLD_MAX = 6;
+constexpr int FOLD_THREADS = 512;   // threads of the fold block: 2048 partials per load round
 
 __device__ __forceinline__ void store_partials(const Pools& P, const BodyDev& B, int blk, const double* v,
                                                int nval) {
@@ -259,29 +260,29 @@ __device__ __forceinline__ void store_partials(const Pools& P, const BodyDev& B,
 
 template <int NVAL>
 __device__ void fold_partials(const Pools& P, const BodyDev& B, int nblk, double* out) {
-    __shared__ double s_red[FOLD_MAX][256];
+    __shared__ double s_red[FOLD_MAX][FOLD_THREADS];
     const int t = threadIdx.x;
     double acc[NVAL];
     for (int i = 0; i < NVAL; ++i) acc[i] = 0.0;
     // four slots per round, loaded together; summed in ascending block order
-    for (int k0 = t; k0 < nblk; k0 += 4 * 256) {
+    for (int k0 = t; k0 < nblk; k0 += 4 * FOLD_THREADS) {
         double v[4][NVAL];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u * 256;
+            const int k = k0 + u * FOLD_THREADS;
             const double* slot = P.partial + 16LL * (B.red_slot + (k < nblk ? k : 0));
 #pragma unroll
             for (int i = 0; i < NVAL; ++i) v[u][i] = slot[i];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (k0 + u * 256 < nblk)
+            if (k0 + u * FOLD_THREADS < nblk)
 #pragma unroll
                 for (int i = 0; i < NVAL; ++i) acc[i] += v[u][i];
     }
     for (int i = 0; i < NVAL; ++i) s_red[i][t] = acc[i];
     __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
+    for (int w = FOLD_THREADS / 2; w >= 1; w >>= 1) {
         if (t < w)
             for (int i = 0; i < NVAL; ++i) s_red[i][t] += s_red[i][t + w];
         __syncthreads();
@@ -769,7 +770,7 @@ __device__ bool rigid_update(const BodyDev& B, BodyState& S, const double tot[6]
 // One block per body.  mode 0 (after the centroid kernel): enclosed volume V^n of membranes
 // with a volume penalty; mode 1 (after the probe kernel): hydrodynamic totals and the velocity
 // / pose update of rigid bodies.  Other bodies return at once.
-__global__ void __launch_bounds__(256) k_fold_bodies(Pools P, int mode) {
+__global__ void __launch_bounds__(FOLD_THREADS) k_fold_bodies(Pools P, int mode) {
     const int b = blockIdx.x;
     const BodyDev& B = P.bodies[b];
     if (mode == 0 ? (B.rigid || B.kv == 0.0) : !B.rigid) return;
@@ -989,7 +990,7 @@ void launch_windows(const Pools& P, int nbodies, hipStream_t s) {
     if (nbodies > 0) hipLaunchKernelGGL(k_windows, dim3(nbodies), dim3(256), 0, s, P);
 }
 void launch_fold_bodies(const Pools& P, int nbodies, int mode, hipStream_t s) {
-    if (nbodies > 0) hipLaunchKernelGGL(k_fold_bodies, dim3(nbodies), dim3(256), 0, s, P, mode);
+    if (nbodies > 0) hipLaunchKernelGGL(k_fold_bodies, dim3(nbodies), dim3(FOLD_THREADS), 0, s, P, mode);
 }
 
 void launch_triangles(const Pools& P, int nblk_tri, int nblk_vel, hipStream_t s) {

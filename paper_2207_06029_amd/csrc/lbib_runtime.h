@@ -52,6 +52,9 @@ struct HostBody {
 lbib_status build_body(const lbib_body_desc& d, const double* xyz, int nv, const int* tri, int nt,
                        HostBody& hb);
 
+// steps per captured graph (even: the population buffers swap once per step)
+constexpr int GRAPH_STEPS = 16;
+
 struct Batch {
     hipStream_t stream = nullptr;
     int device = -1;           // HIP device current when the batch was created

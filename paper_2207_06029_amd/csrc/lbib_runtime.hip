@@ -831,16 +831,20 @@ lbib_status Batch::step(int nsteps, bool collide) {
         if ((st = prime())) return st;
     if (!collide) primed = false;
     if (use_graph && collide && !timing) {
-        // a graph holds two steps (A->B, B->A) so the buffer parity returns to the start
+        // a graph holds GRAPH_STEPS steps (an even count, so the buffer parity returns to the
+        // start); each replay costs a launch gap of several microseconds, which the steps share
         int k = 0;
         if (cur_b && nsteps > 0) { if ((st = enqueue_step(true))) return st; k = 1; ++step_count; }
-        const int pairs = (nsteps - k) / 2;
-        if (pairs > 0) {
+        const int reps = (nsteps - k) / GRAPH_STEPS;
+        if (reps > 0) {
             if (!graph_valid) { if ((st = capture_graph())) return st; }
-            for (int p = 0; p < pairs; ++p) HIP_TRY(hipGraphLaunch(graph_exec, stream));
-            step_count += 2LL * pairs;
+            for (int p = 0; p < reps; ++p) HIP_TRY(hipGraphLaunch(graph_exec, stream));
+            step_count += (long long)GRAPH_STEPS * reps;
         }
-        if ((nsteps - k) % 2) { if ((st = enqueue_step(true))) return st; ++step_count; }
+        for (int r = k + reps * GRAPH_STEPS; r < nsteps; ++r) {
+            if ((st = enqueue_step(true))) return st;
+            ++step_count;
+        }
         return LBIB_OK;
     }
     hipEvent_t s0 = nullptr, s1 = nullptr;
@@ -867,11 +871,11 @@ lbib_status Batch::capture_graph() {
     hipStream_t user = stream;
     HIP_TRY(hipStreamSynchronize(user));
     HIP_TRY(hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal));
-    // launches of the two steps go to the capture stream; the caller's stream is restored below
+    // launches of the steps go to the capture stream; the caller's stream is restored below
     stream = capture_stream;
     const bool start_b = cur_b;
-    lbib_status st = enqueue_step(true);
-    if (!st) st = enqueue_step(true);
+    lbib_status st = LBIB_OK;
+    for (int i = 0; i < GRAPH_STEPS && !st; ++i) st = enqueue_step(true);
     hipError_t e = hipStreamEndCapture(stream, &graph);
     stream = user;
     cur_b = start_b;
