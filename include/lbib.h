@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LBIB_ABI_VERSION 1u
+#define LBIB_ABI_VERSION 2u
 
 typedef enum {
     LBIB_OK = 0,
@@ -239,14 +239,17 @@ lbib_status lbib_batch_launch_shape(const lbib_batch* b, int32_t* block, int32_t
 /* ---------------------------------------------------------------- serving */
 
 typedef struct {
-    uint64_t hbm_budget_bytes;   /* device memory the resident jobs may occupy */
-    int32_t max_slots;           /* jobs resident at once */
+    uint64_t hbm_budget_bytes;   /* device memory the slots may occupy */
+    int32_t max_slots;           /* jobs resident at once, at most */
     int32_t steps_per_tick;      /* steps every resident job advances per tick */
     int32_t storage;             /* lbib_storage of every job */
-    int32_t use_graph;
+    int32_t use_graph;           /* ignored: the server launches eagerly over its live tables */
     int32_t dry_run;             /* 1: schedule only (admission, ticks, retirement) without any
                                     device work; results carry no state.  For policy tests. */
     int32_t pad;
+    int64_t slot_nodes;          /* lattice nodes a slot holds; 0: 128*64*128 */
+    int32_t slot_vertices;       /* mesh vertices a slot holds; 0: 10242 (a level-5 icosphere) */
+    int32_t slot_triangles;      /* mesh triangles a slot holds; 0: 2 slot_vertices - 4 */
 } lbib_server_opts;
 
 typedef struct {
@@ -260,10 +263,15 @@ typedef struct {
     double* xyz;                 /* caller buffer of 3*nv doubles for final positions, or NULL */
 } lbib_result;
 
-/* Continuous-batching server: submitted jobs wait in FIFO order and are admitted when a slot
- * is free and their device bytes fit the budget; admitted jobs stay resident and advance
- * together in one batched launch per kernel; finished jobs retire and free their slot and
- * memory at the next tick.  Errors: EINVAL, ENOMEM (a job that can never fit the budget). */
+/* Continuous-batching server (the serving pattern of the scope table: admission, splice at a
+ * tick, retirement).  At creation the server sizes min(max_slots, hbm_budget_bytes / slot
+ * bytes) slots, each holding any job up to the slot capacity (populations, windows, mesh arrays
+ * and table entries), and allocates nothing afterwards.  Submitted jobs wait in FIFO order; at a
+ * tick each queued job is spliced into a free slot (its table entries and state written in
+ * place, resident jobs untouched) at rest with step counter 0; resident jobs advance together
+ * in one launch per kernel; finished jobs retire and free their slot.  A job's results are
+ * bitwise those of the same job run alone.  Errors: EINVAL, ENOMEM (the budget holds no slot,
+ * or the job exceeds the slot capacity), EDEVICE. */
 lbib_status lbib_server_create(const lbib_server_opts* opts, void* hip_stream, lbib_server** out);
 lbib_status lbib_server_destroy(lbib_server* s);
 /* Queue a job (copies its mesh); never blocks.  t_submit is taken now. */
@@ -273,9 +281,14 @@ lbib_status lbib_server_tick(lbib_server* s);
 /* Copy up to cap finished results (oldest first) into out; *n receives the count.  The xyz
  * pointer of each out[i] must be set by the caller (or NULL). */
 lbib_status lbib_server_poll(lbib_server* s, lbib_result* out, int32_t cap, int32_t* n);
-/* Queue length, resident jobs, resident bytes, lattice node updates done so far. */
+/* Queue length, resident jobs, device bytes of the occupied slots, lattice node updates done so
+ * far. */
 lbib_status lbib_server_stats(const lbib_server* s, int32_t* queued, int32_t* resident,
                               uint64_t* resident_bytes, double* node_updates);
+/* Slot count, device bytes per slot, and device bytes the server has allocated (constant after
+ * creation; 0 in dry-run mode).  Any output may be NULL. */
+lbib_status lbib_server_info(const lbib_server* s, int32_t* slots, uint64_t* slot_bytes,
+                             uint64_t* device_bytes);
 
 #ifdef __cplusplus
 }

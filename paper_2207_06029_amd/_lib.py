@@ -55,7 +55,8 @@ class lbib_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("steps_per_tick", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("dry_run", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("pad", ctypes.c_int32), ("slot_nodes", ctypes.c_int64),
+                ("slot_vertices", ctypes.c_int32), ("slot_triangles", ctypes.c_int32)]
 
 
 class lbib_result(ctypes.Structure):
@@ -106,6 +107,7 @@ SIGNATURES = {
     "lbib_server_tick": (ctypes.c_int, [_P]),
     "lbib_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(lbib_result), ctypes.c_int32, _I32]),
     "lbib_server_stats": (ctypes.c_int, [_P, _I32, _I32, ctypes.POINTER(ctypes.c_uint64), _D]),
+    "lbib_server_info": (ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 _lib = None

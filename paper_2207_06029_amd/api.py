@@ -246,10 +246,12 @@ class Batch:
 
 
 class Server:
-    """lbib_server: continuous batching with memory-budget admission."""
+    """lbib_server: continuous batching over slots sized once for the memory budget; jobs are
+    spliced into free slots and retired in place."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int, steps_per_tick: int,
-                 storage: int = 1, use_graph: bool = False, stream=None, dry_run: bool = False):
+                 storage: int = 1, use_graph: bool = False, stream=None, dry_run: bool = False,
+                 slot_nodes: int = 0, slot_vertices: int = 0, slot_triangles: int = 0):
         self._lib = L.load()
         o = L.lbib_server_opts()
         o.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -258,6 +260,9 @@ class Server:
         o.storage = int(storage)
         o.use_graph = int(bool(use_graph))
         o.dry_run = int(bool(dry_run))
+        o.slot_nodes = int(slot_nodes)
+        o.slot_vertices = int(slot_vertices)
+        o.slot_triangles = int(slot_triangles)
         h = ctypes.c_void_p()
         L.check(self._lib.lbib_server_create(ctypes.byref(o), _stream_handle(stream), ctypes.byref(h)))
         self._h = h
@@ -315,3 +320,9 @@ class Server:
         nu = ctypes.c_double()
         L.check(self._lib.lbib_server_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b), ctypes.byref(nu)))
         return dict(queued=q.value, resident=r.value, resident_bytes=b.value, node_updates=nu.value)
+
+    def info(self):
+        s = ctypes.c_int32()
+        sb, db = ctypes.c_uint64(), ctypes.c_uint64()
+        L.check(self._lib.lbib_server_info(self._h, ctypes.byref(s), ctypes.byref(sb), ctypes.byref(db)))
+        return dict(slots=s.value, slot_bytes=sb.value, device_bytes=db.value)

@@ -501,7 +501,7 @@ __global__ void __launch_bounds__(IB_BLOCK) k_centroids(Pools P, int nblk_tri, i
     if (fold) {
         // every vertex-block box, loaded now so that these loads overlap the MLS work
         for (int q = threadIdx.x; q < B.nblk_v; q += blockDim.x) {
-            const int* e = P.vbox + 6LL * (B.blk_v0 + q);
+            const int* e = P.vbox + 6LL * (B.vbox0 + q);
             for (int a = 0; a < 3; ++a) { vb[a] = min(vb[a], e[a]); vb[3 + a] = max(vb[3 + a], e[3 + a]); }
         }
     } else {
@@ -773,6 +773,7 @@ __device__ bool rigid_update(const BodyDev& B, BodyState& S, const double tot[6]
 __global__ void __launch_bounds__(FOLD_THREADS) k_fold_bodies(Pools P, int mode) {
     const int b = blockIdx.x;
     const BodyDev& B = P.bodies[b];
+    if (B.nv == 0) return;   // an empty slot of a slotted batch
     if (mode == 0 ? (B.rigid || B.kv == 0.0) : !B.rigid) return;
     double tot[FOLD_MAX];
     if (mode == 0) fold_partials<1>(P, B, B.nblk_c, tot);
@@ -900,7 +901,7 @@ __global__ void __launch_bounds__(VERT_BLOCK) k_vertices(Pools P) {
     if (err) atomicOr(P.flags + B.job, err);
     __syncthreads();
     if (threadIdx.x == 0) {
-        int* vb = P.vbox + 6LL * blockIdx.x;
+        int* vb = P.vbox + 6LL * (B.vbox0 + blk);
         for (int a = 0; a < 3; ++a) {
             int lo = box[0][a], hi = box[0][3 + a];
             for (int g = 1; g < VERT_PER_BLOCK; ++g) { lo = min(lo, box[g][a]); hi = max(hi, box[g][3 + a]); }
@@ -917,12 +918,13 @@ __global__ void __launch_bounds__(VERT_BLOCK) k_vertices(Pools P) {
 __global__ void __launch_bounds__(256) k_windows(Pools P) {
     const int b = blockIdx.x;
     const BodyDev& B = P.bodies[b];
+    if (B.nv == 0) return;   // an empty slot of a slotted batch
     const JobDev& J = P.jobs[B.job];
     __shared__ int red[6][256];
     const int t = threadIdx.x;
     int e[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -0x7fffffff, -0x7fffffff, -0x7fffffff};
     for (int q = t; q < B.nblk_v; q += 256) {
-        const int* vb = P.vbox + 6LL * (B.blk_v0 + q);
+        const int* vb = P.vbox + 6LL * (B.vbox0 + q);
         for (int a = 0; a < 3; ++a) { e[a] = min(e[a], vb[a]); e[3 + a] = max(e[3 + a], vb[3 + a]); }
     }
     for (int a = 0; a < 6; ++a) red[a][t] = e[a];

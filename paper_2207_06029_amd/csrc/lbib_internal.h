@@ -126,6 +126,7 @@ struct BodyDev {
     // first block of this body in the centroid / edge / triangle / vertex grids, block counts
     int blk_c0, nblk_c, blk_e0, nblk_e, blk_t0, nblk_t, blk_v0, nblk_v, blk_w0, nblk_w;
     int blk_u0, nblk_u;   // vertex-velocity blocks of the probe launch
+    int vbox0;            // first of the body's nblk_v integer boxes in the vertex-box pool
     double kb, kv, mv, V0, mass;
     double rw, alpha, probe, shell_h;
     double rw2;                 // r_w^2: support test on squared distances

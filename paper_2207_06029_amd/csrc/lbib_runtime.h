@@ -51,9 +51,21 @@ struct HostBody {
 
 lbib_status build_body(const lbib_body_desc& d, const double* xyz, int nv, const int* tri, int nt,
                        HostBody& hb);
+void body_record(const HostBody& h, const JobDev& J, BodyDev& B);
+void incidence_lists(const HostBody& h, int wt, int wh, std::vector<int>& vtl, std::vector<int>& vhl);
 
 // steps per captured graph (even: the population buffers swap once per step)
 constexpr int GRAPH_STEPS = 16;
+
+// Capacity of one slot of a slotted batch: every job admitted to the slot must fit it.
+struct SlotCaps {
+    long long nodes = 0;   // lattice nodes
+    int nv = 0, nt = 0;    // mesh vertices and triangles
+};
+// incidence-list widths a slot holds (vertex valence up to WS_MAX_VALENCE)
+constexpr int SLOT_VT_W = WS_MAX_VALENCE;
+constexpr int SLOT_VH_W = 2 * WS_MAX_VALENCE;
+uint64_t slot_device_bytes(const SlotCaps& c, int storage);
 
 struct Batch {
     hipStream_t stream = nullptr;
@@ -125,6 +137,22 @@ struct Batch {
     lbib_status body_forces(int bi, double* fv, double* F, double* M);
     lbib_status body_set_velocity(int bi, const double* v);
     size_t device_bytes() const;
+
+    // Slotted batches (the server).  Every pool, table and window is sized once for nslots
+    // slots of capacity caps; jobs are spliced into a slot and out again in place: their job,
+    // tile and block table entries are rewritten, nothing is reallocated or copied between
+    // slots.  Steps launch eagerly over the live tables.
+    bool slotted = false;
+    SlotCaps caps{};
+    std::vector<char> slot_live;
+    int tiles_slot = 0;              // per-slot capacities: sweep tiles, blocks of each launch
+    int bc_slot = 0, be_slot = 0, bt_slot = 0, bu_slot = 0, bv_slot = 0, bw_slot = 0, red_slot = 0;
+    long long ne_slot = 0, win_slot = 0;
+    lbib_status create_slotted(int nslots, const SlotCaps& c, int storage, void* stream);
+    // Splice a job into free slot s (hb: its body, or null), at rest, step counter 0.
+    lbib_status slot_admit(int s, const lbib_lattice_desc& d, const HostBody* hb);
+    lbib_status slot_retire(int s);
+    lbib_status slot_tables();
     ~Batch();
 };
 

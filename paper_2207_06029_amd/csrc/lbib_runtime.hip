@@ -474,6 +474,44 @@ lbib_status Batch::set_shape(SweepShape s) {
 }
 
 // Re-create every body-related device pool from the host copies (after a body was added).
+// The record of body h in lattice J, without its placement (offsets and block ranges).
+void body_record(const HostBody& h, const JobDev& J, BodyDev& B) {
+    std::memset(&B, 0, sizeof B);
+    B.job = h.job; B.rigid = h.desc.rigid; B.integrator = h.desc.integrator;
+    B.nv = h.nv; B.nt = h.nt; B.ne = h.ne;
+    // padded incidence lists: width = the largest count of any vertex of this body
+    int wt = 1, wh = 1;
+    for (int v = 0; v < h.nv; ++v) {
+        wt = std::max(wt, h.vt_ptr[v + 1] - h.vt_ptr[v]);
+        wh = std::max(wh, h.vh_ptr[v + 1] - h.vh_ptr[v]);
+    }
+    B.vt_w = wt;
+    B.vh_w = wh;
+    B.kb = h.desc.kb; B.kv = h.desc.kv; B.mv = h.mv; B.V0 = h.V0; B.mass = h.mass;
+    B.rw = h.desc.mls_rw; B.alpha = h.desc.mls_alpha; B.probe = h.desc.probe_len; B.shell_h = h.desc.shell_h;
+    B.rw2 = h.desc.mls_rw * h.desc.mls_rw;
+    B.wq = (float)(1.0 / (B.rw2 * h.desc.mls_alpha * h.desc.mls_alpha));
+    for (int a = 0; a < 3; ++a) B.gravity[a] = h.desc.gravity[a];
+    for (int k = 0; k < 9; ++k) B.Ib[k] = h.Ib[k];
+    const int dims[3] = {J.nx, J.ny, J.nz};
+    window_capacity(dims, h.desc.rigid != 0, h.rbound, B.win_cap);
+}
+
+// Append body h's incidence lists padded to widths wt (triangles) and wh (hinge roles), -1 past
+// a vertex's own count.
+void incidence_lists(const HostBody& h, int wt, int wh, std::vector<int>& vtl, std::vector<int>& vhl) {
+    for (int v = 0; v < h.nv; ++v) {
+        for (int j = 0; j < wt; ++j) {
+            const int q = h.vt_ptr[v] + j;
+            vtl.push_back(q < h.vt_ptr[v + 1] ? h.vt_list[q] : -1);
+        }
+        for (int j = 0; j < wh; ++j) {
+            const int q = h.vh_ptr[v] + j;
+            vhl.push_back(q < h.vh_ptr[v + 1] ? h.vh_list[q] : -1);
+        }
+    }
+}
+
 lbib_status Batch::rebuild_bodies() {
     lbib_status st;
     if ((st = download_body_state())) return st;
@@ -496,38 +534,11 @@ lbib_status Batch::rebuild_bodies() {
         if (J.nbodies == 0) J.body0 = (int)i;
         J.nbodies++;
         BodyDev& B = bd[i];
-        std::memset(&B, 0, sizeof B);
-        B.job = h.job; B.rigid = h.desc.rigid; B.integrator = h.desc.integrator;
-        B.nv = h.nv; B.nt = h.nt; B.ne = h.ne;
+        body_record(h, J, B);
         B.v0 = v0; B.t0 = t0; B.e0 = e0;
-        // padded incidence lists: width = the largest count of any vertex of this body
-        int wt = 1, wh = 1;
-        for (int v = 0; v < h.nv; ++v) {
-            wt = std::max(wt, h.vt_ptr[v + 1] - h.vt_ptr[v]);
-            wh = std::max(wh, h.vh_ptr[v + 1] - h.vh_ptr[v]);
-        }
         B.vt_off = (long long)vtl.size();
         B.vh_off = (long long)vhl.size();
-        B.vt_w = wt;
-        B.vh_w = wh;
-        for (int v = 0; v < h.nv; ++v) {
-            for (int j = 0; j < wt; ++j) {
-                const int q = h.vt_ptr[v] + j;
-                vtl.push_back(q < h.vt_ptr[v + 1] ? h.vt_list[q] : -1);
-            }
-            for (int j = 0; j < wh; ++j) {
-                const int q = h.vh_ptr[v] + j;
-                vhl.push_back(q < h.vh_ptr[v + 1] ? h.vh_list[q] : -1);
-            }
-        }
-        B.kb = h.desc.kb; B.kv = h.desc.kv; B.mv = h.mv; B.V0 = h.V0; B.mass = h.mass;
-        B.rw = h.desc.mls_rw; B.alpha = h.desc.mls_alpha; B.probe = h.desc.probe_len; B.shell_h = h.desc.shell_h;
-        B.rw2 = h.desc.mls_rw * h.desc.mls_rw;
-        B.wq = (float)(1.0 / (B.rw2 * h.desc.mls_alpha * h.desc.mls_alpha));
-        for (int a = 0; a < 3; ++a) B.gravity[a] = h.desc.gravity[a];
-        for (int k = 0; k < 9; ++k) B.Ib[k] = h.Ib[k];
-        const int dims[3] = {J.nx, J.ny, J.nz};
-        window_capacity(dims, h.desc.rigid != 0, h.rbound, B.win_cap);
+        incidence_lists(h, B.vt_w, B.vh_w, vtl, vhl);
         const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
         B.win_off = woff;
         woff += capn;
@@ -539,6 +550,7 @@ lbib_status Batch::rebuild_bodies() {
         B.blk_c0 = nblk_c; B.nblk_c = nbc; nblk_c += nbc;
         B.blk_e0 = nblk_e; B.nblk_e = nbe; nblk_e += nbe;
         B.blk_t0 = nblk_t; B.nblk_t = nbt; nblk_t += nbt;
+        B.vbox0 = nblk_v;
         B.blk_v0 = nblk_v; B.nblk_v = nbv; nblk_v += nbv;
         B.blk_u0 = nblk_u; B.nblk_u = nbu; nblk_u += nbu;
         const int nbw = (int)std::max<long long>(1, (capn + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
@@ -987,6 +999,311 @@ lbib_status Batch::body_set_velocity(int bi, const double* v) {
 
 size_t Batch::device_bytes() const {
     return arena.base ? arena.used : arena.total;
+}
+
+// ---------------------------------------------------------------- slotted batches
+// Device bytes one slot of capacity c occupies (create_slotted allocates nslots times this, plus
+// 48 bytes of totals, each allocation rounded up to 256 bytes).
+uint64_t slot_device_bytes(const SlotCaps& c, int storage) {
+    const uint64_t es = storage_bytes(storage), per = 256;
+    const uint64_t nodes = (uint64_t)std::max<long long>(c.nodes, 1), nv = (uint64_t)c.nv, nt = (uint64_t)c.nt;
+    const uint64_t ne = 3 * nt / 2, win = nodes;
+    const uint64_t bc = (nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, bt = (nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
+    const uint64_t bu = (nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, bv = (nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK;
+    const uint64_t be = (ne + IB_BLOCK - 1) / IB_BLOCK;
+    const uint64_t bw = std::max<uint64_t>(1, (win + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
+    uint64_t b = 2 * 19 * nodes * es + 4 + 8 + sizeof(JobDev) + sizeof(int4) * ((nodes + per - 1) / per);
+    b += sizeof(BodyDev) + 4 * (bc + be + bt + bv + bu + bw);
+    b += 6 * 24 * nv + 12 * nt + 8 * ne + 16 * ne + 3 * 8 * ne;
+    b += 4 * nv * SLOT_VT_W + 4 * nv * SLOT_VH_W;
+    b += 48 * nt + 24 * nt + 24 * nt + 120 * ne + 24 * win + 16 * win;
+    b += 2 * sizeof(WinDesc) + sizeof(BodyState) + 128 * std::max(bc, bt) + 24 * bv;
+    return b + 40 * 256;
+}
+
+lbib_status Batch::create_slotted(int nslots, const SlotCaps& c, int storage_, void* stream_) {
+    if (nslots < 1 || c.nodes < 1 || c.nv < 0 || c.nt < 0) return fail(LBIB_EINVAL, "bad slot capacity");
+    stream = (hipStream_t)stream_;
+    storage = storage_;
+    HIP_TRY(hipGetDevice(&device));
+    slotted = true;
+    caps = c;
+    slot_live.assign(nslots, 0);
+    const size_t es = storage_bytes(storage);
+    const long long per = (long long)shape.block * shape.npt;
+    tiles_slot = (int)((c.nodes + per - 1) / per);
+    ne_slot = 3LL * c.nt / 2;
+    win_slot = c.nodes;   // a window never exceeds its lattice
+    bc_slot = (c.nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
+    be_slot = (int)((ne_slot + IB_BLOCK - 1) / IB_BLOCK);
+    bt_slot = (c.nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
+    bu_slot = (c.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
+    bv_slot = (c.nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK;
+    bw_slot = (int)std::max<long long>(1, (win_slot + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
+    red_slot = std::max(bc_slot, bt_slot);
+    const long long S = nslots;
+    // lattices: empty slots hold no job (n = 0)
+    jobs.assign(nslots, JobDev{});
+    for (int j = 0; j < nslots; ++j) jobs[j].pop_off = (long long)j * 19 * c.nodes;
+    ldesc.assign(nslots, lbib_lattice_desc{});
+    pop_elems = S * 19 * c.nodes;
+    P.pop32 = 19LL * c.nodes * (long long)es < (1LL << 32) ? 1 : 0;
+    void* p;
+    lbib_status st;
+    if ((st = arena.alloc(pop_elems * es, &P.popA))) return st;
+    if ((st = arena.alloc(pop_elems * es, &P.popB))) return st;
+    if ((st = arena.alloc(sizeof(int) * S, &p))) return st;
+    P.flags = (int*)p;
+    HIP_TRY(hipMemsetAsync(P.flags, 0, sizeof(int) * S, stream));
+    if ((st = arena.alloc(sizeof(unsigned) * 2 * S, &p))) return st;
+    P.sr_ctr = (unsigned*)p;
+    HIP_TRY(hipMemsetAsync(P.sr_ctr, 0, sizeof(unsigned) * 2 * S, stream));
+    if ((st = arena.alloc(sizeof(JobDev) * S, &p))) return st;
+    d_jobs = (JobDev*)p;
+    P.jobs = d_jobs;
+    tile_cap = (size_t)S * tiles_slot;
+    if ((st = arena.alloc(sizeof(int4) * tile_cap, &p))) return st;
+    d_tiles = (int4*)p;
+    P.tiles = d_tiles;
+    xcd_chunk = shape.xcd_chunk >= 0 ? shape.xcd_chunk : (2 * pop_elems * (long long)es <= XCD_CHUNK_MAX_BYTES ? XCD_CHUNK : 0);
+    // bodies: one per slot, every array sized for the slot's capacity
+    auto take = [&](size_t bytes, void** out) { return arena.alloc(std::max<size_t>(bytes, 1), out); };
+    if ((st = take(sizeof(BodyDev) * S, &p))) return st;
+    d_bodies = (BodyDev*)p;
+    P.bodies = d_bodies;
+    const int* tables[6];
+    const long long tsz[6] = {S * bc_slot, S * be_slot, S * bt_slot, S * bv_slot, S * bu_slot, S * bw_slot};
+    for (int k = 0; k < 6; ++k) {
+        if ((st = take(sizeof(int) * tsz[k], &p))) return st;
+        tables[k] = (const int*)p;
+    }
+    P.blk_body_c = tables[0]; P.blk_body_e = tables[1]; P.blk_body_t = tables[2];
+    P.blk_body_v = tables[3]; P.blk_body_u = tables[4]; P.blk_body_w = tables[5];
+    const size_t nv3 = sizeof(double) * 3 * (size_t)(S * c.nv);
+    double** vec3[6] = {&P.x, &P.xprev, &P.uv, &P.fv, &P.u0v, (double**)&P.xb};
+    for (auto q : vec3) {
+        if ((st = take(nv3, &p))) return st;
+        *q = (double*)p;
+    }
+    HIP_TRY(hipMemsetAsync(P.fv, 0, nv3, stream));
+    HIP_TRY(hipMemsetAsync(P.u0v, 0, nv3, stream));
+    if ((st = take(sizeof(int) * 3 * (size_t)(S * c.nt), &p))) return st;
+    P.tri = (const int*)p;
+    if ((st = take(sizeof(int) * 2 * (size_t)(S * ne_slot), &p))) return st;
+    P.edge = (const int*)p;
+    if ((st = take(sizeof(int) * 4 * (size_t)(S * ne_slot), &p))) return st;
+    P.hinge = (const int*)p;
+    const double** rest[3] = {&P.l0, &P.ks, &P.theta0};
+    for (auto q : rest) {
+        if ((st = take(sizeof(double) * (size_t)(S * ne_slot), &p))) return st;
+        *q = (const double*)p;
+    }
+    if ((st = take(sizeof(int) * (size_t)(S * c.nv) * SLOT_VT_W, &p))) return st;
+    P.vt_list = (const int*)p;
+    if ((st = take(sizeof(int) * (size_t)(S * c.nv) * SLOT_VH_W, &p))) return st;
+    P.vh_list = (const int*)p;
+    if ((st = take(sizeof(double) * 6 * (size_t)(S * c.nt), &p))) return st;
+    P.tgeo = (double*)p;
+    if ((st = take(sizeof(double) * 3 * (size_t)(S * c.nt), &p))) return st;
+    P.fext = (double*)p;
+    if ((st = take(sizeof(double) * 3 * (size_t)(S * c.nt), &p))) return st;
+    P.fvol = (double*)p;
+    if ((st = take(sizeof(double) * 15 * (size_t)(S * ne_slot), &p))) return st;
+    P.fedge = (double*)p;
+    if ((st = take(sizeof(long long) * 3 * (size_t)(S * win_slot), &p))) return st;
+    P.fwin = (long long*)p;
+    HIP_TRY(hipMemsetAsync(P.fwin, 0, sizeof(long long) * 3 * (size_t)(S * win_slot), stream));
+    if ((st = take(sizeof(float4) * (size_t)(S * win_slot), &p))) return st;
+    P.mwin = (float4*)p;
+    HIP_TRY(hipMemsetAsync(P.mwin, 0, sizeof(float4) * (size_t)(S * win_slot), stream));
+    if ((st = take(sizeof(WinDesc) * S, &p))) return st;
+    P.fdesc = (WinDesc*)p;
+    if ((st = take(sizeof(WinDesc) * S, &p))) return st;
+    P.mdesc = (WinDesc*)p;
+    if ((st = take(sizeof(BodyState) * S, &p))) return st;
+    P.bstate = (BodyState*)p;
+    if ((st = take(sizeof(double) * 16 * (size_t)(S * red_slot), &p))) return st;
+    P.partial = (double*)p;
+    if ((st = take(sizeof(int) * 6 * (size_t)(S * bv_slot), &p))) return st;
+    P.vbox = (int*)p;
+    if ((st = take(sizeof(double) * 6, &p))) return st;
+    d_totals = (double*)p;
+    // every slot starts empty; the body tables keep one (empty) body per slot
+    nbodies = nslots;
+    hbodies.assign(nslots, HostBody{});
+    host_bodies.assign(nslots, BodyDev{});
+    for (int j = 0; j < nslots; ++j) {
+        hbodies[j].job = j;
+        host_bodies[j].job = j;
+    }
+    P.solo_job = -1;
+    any_rigid = any_volume = true;   // the fold launches skip bodies without that work
+    use_graph = false;
+    primed = true;   // admissions prime their own moment windows
+    lbib_status r = slot_tables();
+    if (r) return r;
+    HIP_TRY(hipStreamSynchronize(stream));
+    return LBIB_OK;
+}
+
+// Packed tables of the live slots (tiles and blocks in slot order) and the job and body records,
+// copied over the fixed-size device tables; the launch grids follow the live counts.
+lbib_status Batch::slot_tables() {
+    const int S = (int)slot_live.size();
+    const long long per = (long long)shape.block * shape.npt;
+    tiles.clear();
+    std::vector<int> bc, be, bt, bv, bu, bw;
+    for (int s = 0; s < S; ++s) {
+        JobDev& J = jobs[s];
+        BodyDev& B = host_bodies[s];
+        if (!slot_live[s]) {
+            J.n = 0; J.tile0 = J.ntiles = 0; J.nbodies = 0;
+            continue;
+        }
+        J.tile0 = (int)tiles.size();
+        J.ntiles = (int)((J.n + per - 1) / per);
+        for (int t = 0; t < J.ntiles; ++t) {
+            const long long k0 = (long long)t * per, q = k0 / J.nx;
+            tiles.push_back(make_int4(s, (int)(k0 - q * J.nx), (int)(q % J.ny), (int)(q / J.ny)));
+        }
+        if (B.nv == 0) continue;
+        const int nbc = (B.nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbt = (B.nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
+        const int nbu = (B.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbv = (B.nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK;
+        const int nbe = B.rigid ? 0 : (B.ne + IB_BLOCK - 1) / IB_BLOCK;
+        const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+        const int nbw = (int)std::max<long long>(1, (capn + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
+        B.blk_c0 = (int)bc.size(); B.nblk_c = nbc; bc.insert(bc.end(), nbc, s);
+        B.blk_e0 = (int)be.size(); B.nblk_e = nbe; be.insert(be.end(), nbe, s);
+        B.blk_t0 = (int)bt.size(); B.nblk_t = nbt; bt.insert(bt.end(), nbt, s);
+        B.blk_v0 = (int)bv.size(); B.nblk_v = nbv; bv.insert(bv.end(), nbv, s);
+        B.blk_u0 = (int)bu.size(); B.nblk_u = nbu; bu.insert(bu.end(), nbu, s);
+        B.blk_w0 = (int)bw.size(); B.nblk_w = nbw; bw.insert(bw.end(), nbw, s);
+    }
+    auto put = [&](const std::vector<int>& v, const int* dst) -> lbib_status {
+        if (!v.empty()) HIP_TRY(hipMemcpyAsync((void*)dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, stream));
+        return LBIB_OK;
+    };
+    lbib_status st;
+    if ((st = put(bc, P.blk_body_c)) || (st = put(be, P.blk_body_e)) || (st = put(bt, P.blk_body_t)) ||
+        (st = put(bv, P.blk_body_v)) || (st = put(bu, P.blk_body_u)) || (st = put(bw, P.blk_body_w)))
+        return st;
+    if (!tiles.empty())
+        HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(JobDev) * S, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(d_bodies, host_bodies.data(), sizeof(BodyDev) * S, hipMemcpyHostToDevice, stream));
+    nblk_c = (int)bc.size(); nblk_e = (int)be.size(); nblk_t = (int)bt.size();
+    nblk_v = (int)bv.size(); nblk_u = (int)bu.size(); nblk_w = (int)bw.size();
+    // the host copies must stay unchanged until the copies have run
+    HIP_TRY(hipStreamSynchronize(stream));
+    return LBIB_OK;
+}
+
+lbib_status Batch::slot_admit(int s, const lbib_lattice_desc& d, const HostBody* hb) {
+    if (!slotted || s < 0 || s >= (int)slot_live.size() || slot_live[s]) return fail(LBIB_EINVAL, "no such free slot");
+    const long long n = (long long)d.nx * d.ny * d.nz;
+    if (n > caps.nodes) return fail(LBIB_ENOMEM, "lattice exceeds the slot capacity");
+    JobDev J;
+    job_from_desc(d, J);
+    J.pop_off = (long long)s * 19 * caps.nodes;
+    J.body0 = s;
+    J.nbodies = 0;
+    BodyDev B;
+    std::memset(&B, 0, sizeof B);
+    B.job = s;
+    if (hb) {
+        if (hb->nv > caps.nv || hb->nt > caps.nt || hb->ne > ne_slot)
+            return fail(LBIB_ENOMEM, "mesh exceeds the slot capacity");
+        HostBody h = *hb;
+        h.job = s;
+        lbib_status st = check_support(J, h);
+        if (st) return st;
+        body_record(h, J, B);
+        if (B.vt_w > SLOT_VT_W || B.vh_w > SLOT_VH_W) return fail(LBIB_ENOMEM, "vertex valence exceeds the slot capacity");
+        const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+        if (capn > win_slot) return fail(LBIB_ENOMEM, "force window exceeds the slot capacity");
+        B.v0 = (long long)s * caps.nv;
+        B.t0 = (long long)s * caps.nt;
+        B.e0 = (long long)s * ne_slot;
+        B.vt_off = (long long)s * caps.nv * SLOT_VT_W;
+        B.vh_off = (long long)s * caps.nv * SLOT_VH_W;
+        B.win_off = (long long)s * win_slot;
+        B.red_slot = s * red_slot;
+        B.vbox0 = s * bv_slot;
+        J.nbodies = 1;
+        // mesh, rest data and state into the slot's ranges
+        auto put = [&](void* base, size_t elem, long long off, const void* src, size_t count) -> lbib_status {
+            if (count) HIP_TRY(hipMemcpyAsync((char*)base + elem * off, src, elem * count, hipMemcpyHostToDevice, stream));
+            return LBIB_OK;
+        };
+        std::vector<int> vtl, vhl;
+        incidence_lists(h, B.vt_w, B.vh_w, vtl, vhl);
+        std::vector<int> vb;
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int v = 0; v < h.nv; ++v)
+            for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], h.x[3 * v + a]); hi[a] = std::max(hi[a], h.x[3 * v + a]); }
+        const int nbv = (h.nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK;
+        for (int k = 0; k < nbv; ++k) {
+            for (int a = 0; a < 3; ++a) vb.push_back((int)std::floor(lo[a]));
+            for (int a = 0; a < 3; ++a) vb.push_back((int)std::ceil(hi[a]));
+        }
+        bool over = false;
+        const WinDesc fd = window_for(J, lo, hi, B.win_cap, &over);
+        if (over) return fail(LBIB_EDOMAIN, "body does not fit its window");
+        BodyState S;
+        std::memset(&S, 0, sizeof S);
+        S.V = h.V0;
+        for (int k = 0; k < 9; ++k) S.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+        for (int a = 0; a < 3; ++a) S.X[a] = h.X0[a];
+        const size_t nv3 = 3 * (size_t)h.nv;
+        if ((st = put(P.x, 8, 3 * B.v0, h.x.data(), nv3)) || (st = put(P.xprev, 8, 3 * B.v0, h.xprev.data(), nv3)) ||
+            (st = put(P.uv, 8, 3 * B.v0, h.uv.data(), nv3)) || (st = put((void*)P.xb, 8, 3 * B.v0, h.xb.data(), nv3)) ||
+            (st = put((void*)P.tri, 4, 3 * B.t0, h.tri.data(), h.tri.size())) ||
+            (st = put((void*)P.edge, 4, 2 * B.e0, h.edge.data(), h.edge.size())) ||
+            (st = put((void*)P.hinge, 4, 4 * B.e0, h.hinge.data(), h.hinge.size())) ||
+            (st = put((void*)P.l0, 8, B.e0, h.l0.data(), h.l0.size())) ||
+            (st = put((void*)P.ks, 8, B.e0, h.ks.data(), h.ks.size())) ||
+            (st = put((void*)P.theta0, 8, B.e0, h.theta0.data(), h.theta0.size())) ||
+            (st = put((void*)P.vt_list, 4, B.vt_off, vtl.data(), vtl.size())) ||
+            (st = put((void*)P.vh_list, 4, B.vh_off, vhl.data(), vhl.size())) ||
+            (st = put(P.vbox, 4, 6LL * s * bv_slot, vb.data(), vb.size())) ||
+            (st = put(P.fdesc, sizeof(WinDesc), s, &fd, 1)) || (st = put(P.mdesc, sizeof(WinDesc), s, &fd, 1)) ||
+            (st = put(P.bstate, sizeof(BodyState), s, &S, 1)))
+            return st;
+        HIP_TRY(hipMemsetAsync(P.fv + 3 * B.v0, 0, sizeof(double) * nv3, stream));
+        HIP_TRY(hipMemsetAsync(P.u0v + 3 * B.v0, 0, sizeof(double) * nv3, stream));
+        HIP_TRY(hipMemsetAsync(P.fwin + 3 * B.win_off, 0, sizeof(long long) * 3 * (size_t)capn, stream));
+        hbodies[s] = h;
+        hbodies[s].local_id = 0;
+        hbodies[s].has_state = false;
+    }
+    jobs[s] = J;
+    ldesc[s] = d;
+    host_bodies[s] = B;
+    // the job's record first (the initial-state kernel reads it), then the state at rest
+    HIP_TRY(hipMemcpyAsync(d_jobs + s, &jobs[s], sizeof(JobDev), hipMemcpyHostToDevice, stream));
+    launch_init_eq(P, storage, cur_b, s, n, nullptr, nullptr, stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemsetAsync(P.sr_ctr + 2 * s, 0, 2 * sizeof(unsigned), stream));
+    HIP_TRY(hipMemsetAsync(P.flags + s, 0, sizeof(int), stream));
+    slot_live[s] = 1;
+    lbib_status st = slot_tables();
+    if (st) return st;
+    // moment windows of the new body (resident bodies get theirs again, bitwise the same)
+    if (hb) {
+        launch_window_moments(P, storage, cur_b, nblk_w, stream);
+        HIP_TRY(hipGetLastError());
+    }
+    return LBIB_OK;
+}
+
+lbib_status Batch::slot_retire(int s) {
+    if (!slotted || s < 0 || s >= (int)slot_live.size() || !slot_live[s]) return fail(LBIB_EINVAL, "no such live slot");
+    slot_live[s] = 0;
+    std::memset(&host_bodies[s], 0, sizeof(BodyDev));
+    host_bodies[s].job = s;
+    hbodies[s] = HostBody{};
+    hbodies[s].job = s;
+    return slot_tables();
 }
 
 }  // namespace lbib

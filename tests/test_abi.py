@@ -39,10 +39,11 @@ def test_binding_covers_header():
 def test_abi_version_and_struct_sizes(lib):
     from paper_2207_06029_amd import _lib
     lib.lbib_abi_version.restype = ctypes.c_uint32
-    assert lib.lbib_abi_version() == 1
+    assert lib.lbib_abi_version() == 2
     # sizes that follow from the C declarations (natural alignment, 8-byte doubles)
     assert ctypes.sizeof(_lib.lbib_lattice_desc) == 4 * 4 + 8 + 6 * 4 + 18 * 8 + 3 * 8
     assert ctypes.sizeof(_lib.lbib_body_desc) == 2 * 4 + 5 * 8 + 3 * 8 + 4 * 8
+    assert ctypes.sizeof(_lib.lbib_server_opts) == 8 + 6 * 4 + 8 + 2 * 4
 
 
 def test_descriptor_validation_without_gpu(lib):

@@ -140,6 +140,38 @@ def test_server_alone_vs_mix_24_stream_jobs(api):
         alone.destroy()
 
 
+def test_server_splices_jobs_without_allocating(api):
+    """Admissions and retirements write the slot's table entries and state in place: the
+    server's device memory is fixed at creation, slots are reused after a retirement, and every
+    job still ends bitwise like the same job run alone."""
+    jobs = I.serving_stream(seed=11, rate_per_s=1e6, window_s=1.0, storage=I.STORE_F16,
+                            steps_range=(30, 90), levels=(2, 3),
+                            lattices=((32, 32, 32), (40, 32, 40)), max_jobs=10)
+    srv = api.Server(hbm_budget_bytes=1 << 34, max_slots=3, steps_per_tick=20, storage=I.STORE_F16,
+                     slot_vertices=2562)
+    info = srv.info()
+    assert info["slots"] == 3 and info["device_bytes"] > 3 * 2 * 19 * 2 * 128 * 64 * 128
+    ids = {srv.submit(job): job for job in jobs}
+    results, max_res = {}, 0
+    for _ in range(200):
+        srv.tick()
+        max_res = max(max_res, srv.stats()["resident"])
+        assert srv.info()["device_bytes"] == info["device_bytes"]
+        for r in srv.poll(with_positions=True):
+            results[r["id"]] = r
+        if len(results) == len(jobs):
+            break
+    assert len(results) == len(jobs) and max_res == 3
+    for jid, job in ids.items():
+        r = results[jid]
+        assert r["status"] == 0 and r["steps_done"] == job.steps
+        alone = api.Batch([job], storage=I.STORE_F16)
+        alone.step(job.steps)
+        x_a, _ = alone.lattice(0).body_state(0)
+        np.testing.assert_array_equal(r["xyz"], x_a)
+        alone.destroy()
+
+
 def _tune_key(jobs, storage):
     """The tune cache's key of a job mix: storage, then each lattice shape with its count."""
     cnt = {}

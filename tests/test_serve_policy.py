@@ -1,6 +1,6 @@
-"""Serving policy on the CPU: the server in dry-run mode schedules (FIFO admission by slot and
-device-memory budget, lock-step ticks that never overshoot a job's run length, retirement,
-time-to-result stamps) without touching a GPU."""
+"""Serving policy on the CPU: the server in dry-run mode schedules (FIFO admission into the slots
+that the device-memory budget holds, lock-step ticks that never overshoot a job's run length,
+retirement, time-to-result stamps) without touching a GPU."""
 import numpy as np
 import pytest
 
@@ -53,13 +53,18 @@ def test_ticks_never_overshoot_run_length(api):
 
 def test_memory_budget_admission(api):
     one = small_job(1000, 0)      # stays resident after one tick
-    probe = api.Server(hbm_budget_bytes=1 << 40, max_slots=8, steps_per_tick=10, dry_run=True)
+    probe = api.Server(hbm_budget_bytes=1 << 40, max_slots=8, steps_per_tick=10, dry_run=True,
+                       slot_nodes=32 ** 3, slot_vertices=642)
     probe.submit(one)
     probe.tick()
     per_job = probe.stats()["resident_bytes"]
-    assert per_job > 2 * 19 * 24 ** 3 * 2
-    # a budget for two jobs: never more than two resident, the rest wait
-    srv = api.Server(hbm_budget_bytes=2 * per_job + 1, max_slots=8, steps_per_tick=5, dry_run=True)
+    assert per_job == probe.info()["slot_bytes"]
+    assert per_job > 2 * 19 * 32 ** 3 * 2          # both population buffers of a slot
+    assert probe.info()["slots"] == 8 and probe.info()["device_bytes"] == 0
+    # a budget for two slots: never more than two resident, the rest wait
+    srv = api.Server(hbm_budget_bytes=2 * per_job + 1, max_slots=8, steps_per_tick=5, dry_run=True,
+                     slot_nodes=32 ** 3, slot_vertices=642)
+    assert srv.info()["slots"] == 2
     for t in range(5):
         srv.submit(small_job(10, t))
     seen = 0
@@ -72,7 +77,14 @@ def test_memory_budget_admission(api):
 
 
 def test_job_that_never_fits_is_rejected(api):
+    # a budget that holds no slot
     srv = api.Server(hbm_budget_bytes=1 << 20, max_slots=4, steps_per_tick=10, dry_run=True)
+    with pytest.raises(api.L.LbibError) as ei:
+        srv.submit(small_job(10, 0))
+    assert ei.value.code == -2
+    # a job larger than the slots
+    srv = api.Server(hbm_budget_bytes=1 << 40, max_slots=4, steps_per_tick=10, dry_run=True,
+                     slot_nodes=16 ** 3)
     with pytest.raises(api.L.LbibError) as ei:
         srv.submit(small_job(10, 0))
     assert ei.value.code == -2
