@@ -290,70 +290,96 @@ def bench_batch(args) -> dict:
 
 
 def bench_serve(args) -> dict:
-    """Poisson arrivals (mean 4 jobs/s) of capsule-shear and settling jobs served with
-    continuous batching and a device-memory budget; time-to-result percentiles and throughput,
-    then the same stream through a one-job-at-a-time FIFO of the plain FP32 form."""
+    """Serving: Poisson arrivals (mean 4 jobs/s over --serve-window seconds) of capsule-shear and
+    settling jobs, served by the continuous-batching server (FP16, slots sized once for the
+    memory budget).  Time to result runs from each job's arrival time (not its submission);
+    jobs not finished when the run stops are reported as censored with the time they had waited.
+    Capacity, the jobs per hour at saturation, is measured separately by submitting a block of
+    jobs at once.  The plain form is a one-slot FIFO of the same stream with FP32 storage."""
     import numpy as np
     import torch
     from paper_2207_06029_amd import api
     from paper_2207_06029_amd import inputs as I
 
-    def run(stream_jobs, slots, storage, budget, tick):
+    def run(stream_jobs, slots, storage, budget, tick, cutoff_s, label):
         srv = api.Server(hbm_budget_bytes=budget, max_slots=slots, steps_per_tick=tick,
                          storage=storage, stream=torch.cuda.current_stream())
+        info = srv.info()
         pending = sorted(stream_jobs, key=lambda j: j.arrival_s)
-        t_start = time.perf_counter()
-        done, nodes_steps = [], 0.0
-        i = 0
-        last_note = 0.0
+        arrival = {j.tag: j.arrival_s for j in pending}
+        t0_ns = time.monotonic_ns()   # the server stamps steady-clock (monotonic) times
+        done, i, last_note = [], 0, 0.0
         while len(done) < len(pending):
-            now = time.perf_counter() - t_start
+            now = (time.monotonic_ns() - t0_ns) * 1e-9
+            if now > cutoff_s:
+                break
             if now - last_note > 10.0:
                 st = srv.stats()
-                print(f"[serve slots={slots}] t={now:.0f}s submitted={i} done={len(done)} "
+                print(f"[serve {label}] t={now:.0f}s submitted={i} done={len(done)} "
                       f"resident={st['resident']} queued={st['queued']}", file=sys.stderr, flush=True)
                 last_note = now
             while i < len(pending) and pending[i].arrival_s <= now:
                 srv.submit(pending[i])
                 i += 1
             srv.tick()
-            for r in srv.poll():
-                done.append(r)
-            if i < len(pending) and srv.stats()["resident"] == 0 and srv.stats()["queued"] == 0:
-                time.sleep(max(0.0, pending[i].arrival_s - (time.perf_counter() - t_start)))
-            if time.perf_counter() - t_start > args.serve_window * 6 + 120:
-                break
-        wall = time.perf_counter() - t_start
+            done += srv.poll()
+            st = srv.stats()
+            if i < len(pending) and st["resident"] == 0 and st["queued"] == 0:
+                time.sleep(max(0.0, pending[i].arrival_s - (time.monotonic_ns() - t0_ns) * 1e-9))
+        wall = (time.monotonic_ns() - t0_ns) * 1e-9
         st = srv.stats()
-        lat = np.array([(r["t_finish_ns"] - r["t_submit_ns"]) * 1e-9 for r in done])
+        lat = np.array([(r["t_finish_ns"] - t0_ns) * 1e-9 - arrival[r["tag"]] for r in done])
+        finished = {r["tag"] for r in done}
+        arrived = [j for j in pending if j.arrival_s <= wall]
+        waiting = np.array([wall - j.arrival_s for j in arrived if j.tag not in finished])
         ok = sum(1 for r in done if r["status"] == 0)
-        by_tag = {j.tag: j for j in pending}
-        failures = []
-        for r in done:
-            if r["status"] != 0:
-                j = by_tag[r["tag"]]
-                failures.append({"status": r["status"], "kind": j.kind, "dims": [j.lattice.nx, j.lattice.ny, j.lattice.nz],
-                                 "nv": int(len(j.xyz)), "mass_ratio": round(j.body.mass_ratio, 3),
-                                 "ks0": round(j.body.ks0, 5), "kb": round(j.body.kb, 6),
-                                 "tau": round(j.lattice.tau, 3), "steps_done": r["steps_done"]})
-        return {"jobs": len(done), "ok": ok, "failures": failures[:40], "wall_s": round(wall, 2),
-                "jobs_per_hour": round(len(done) / wall * 3600, 1),
+        # percentiles over every arrived job, the censored ones counted as waiting forever: a
+        # percentile that falls on a censored job is reported as None
+        n_arr = len(arrived)
+        allt = np.sort(np.concatenate([lat, np.full(len(waiting), np.inf)])) if n_arr else np.array([])
+        def pct(q):
+            if not n_arr:
+                return None
+            v = allt[min(n_arr - 1, int(np.ceil(q / 100.0 * n_arr)) - 1)]
+            return None if not np.isfinite(v) else round(float(v), 3)
+        return {"jobs_arrived": n_arr, "jobs_finished": len(done), "ok": ok,
+                "censored": int(len(waiting)),
+                "censored_max_wait_s": round(float(waiting.max()), 2) if len(waiting) else 0.0,
+                "wall_s": round(wall, 2), "finished_per_hour": round(len(done) / wall * 3600, 1),
                 "mlups": round(st["node_updates"] / wall / 1e6, 1),
-                "p50_s": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
-                "p99_s": round(float(np.percentile(lat, 99)), 3) if len(lat) else None}
+                "p50_s": pct(50), "p99_s": pct(99),
+                "slots": info["slots"], "slot_bytes": info["slot_bytes"], "device_bytes": info["device_bytes"]}
 
-    jobs = I.serving_stream(seed=0, rate_per_s=4.0, window_s=args.serve_window,
-                            storage=I.STORE_F16)
-    served = run(jobs, slots=64, storage=I.STORE_F16, budget=32 << 30, tick=100)
-    plain = run(I.serving_stream(seed=0, rate_per_s=4.0, window_s=args.serve_window,
-                                 storage=I.STORE_F32), slots=1, storage=I.STORE_F32,
-                budget=32 << 30, tick=100)
-    return {"metric": METRIC, "mode": "serve", "value": served["jobs_per_hour"], "unit": "jobs/h",
-            "served": served, "plain_fifo": plain,
+    budget = 32 << 30
+    jobs = I.serving_stream(seed=0, rate_per_s=4.0, window_s=args.serve_window, storage=I.STORE_F16)
+    served = run(jobs, slots=64, storage=I.STORE_F16, budget=budget, tick=100,
+                 cutoff_s=args.serve_window * 1.5 + 30, label="served")
+    capacity, cap = None, None
+    if args.serve_capacity_jobs > 0:
+        # capacity: a block of jobs of the same stream, all submitted at once
+        block = I.serving_stream(seed=1, rate_per_s=1e6, window_s=1.0, storage=I.STORE_F16,
+                                 max_jobs=args.serve_capacity_jobs)
+        for j in block:
+            j.arrival_s = 0.0
+        cap = run(block, slots=64, storage=I.STORE_F16, budget=budget, tick=100, cutoff_s=600.0,
+                  label="capacity")
+        capacity = round(cap["jobs_finished"] / cap["wall_s"] * 3600, 1)
+    plain, plain_window = None, min(args.serve_window, 60.0)
+    if not args.serve_no_plain:
+        plain = run(I.serving_stream(seed=0, rate_per_s=4.0, window_s=plain_window, storage=I.STORE_F32),
+                    slots=1, storage=I.STORE_F32, budget=budget, tick=100,
+                    cutoff_s=plain_window * 1.5 + 30, label="plain")
+    return {"metric": METRIC, "mode": "serve", "value": capacity, "unit": "jobs/h at saturation",
+            "served": served,
+            "capacity": None if cap is None else {"jobs": cap["jobs_finished"], "wall_s": cap["wall_s"],
+                                                  "jobs_per_hour": capacity, "mlups": cap["mlups"]},
+            "offered_jobs_per_hour": 4.0 * 3600, "plain_fifo": plain,
             "config": {"workload": f"Poisson arrivals 4 jobs/s over {args.serve_window:.0f} s: "
                                    "capsule-shear and settling jobs, lattices 48^3..128x64x128, "
                                    "meshes 642-10242 vertices, 2000-10000 steps, FP16 storage, "
-                                   "32 GiB budget, 64 slots, 100 steps per tick"},
+                                   "32 GiB budget, up to 64 slots, 100 steps per tick; capacity from "
+                                   f"{args.serve_capacity_jobs} jobs submitted at once; plain FIFO "
+                                   f"over the first {plain_window:.0f} s of the stream"},
             "dtype": "f16-storage/f32-compute", "data": "synthetic", "n_gpus": 1}
 
 
@@ -373,7 +399,13 @@ def make_parser() -> argparse.ArgumentParser:
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="prolate128",
                     help="plain mode: prolate capsule in shear at 128x64x128 (default) or 256x128x256, "
                          "or the FP16 rigid sphere settling in a 96x96x384 box")
-    ap.add_argument("--serve-window", type=float, default=60.0)
+    ap.add_argument("--serve-window", type=float, default=60.0,
+                    help="serve mode: seconds of Poisson arrivals (the served run stops at 1.5x "
+                         "this plus 30 s; later results are reported as censored)")
+    ap.add_argument("--serve-capacity-jobs", type=int, default=256,
+                    help="serve mode: jobs submitted at once to measure capacity (0: skip)")
+    ap.add_argument("--serve-no-plain", action="store_true",
+                    help="serve mode: skip the one-slot FIFO of the plain form")
     ap.add_argument("--skip-plain", action="store_true",
                     help="batch mode: time only the batched form (no per-job comparison)")
     ap.add_argument("--sources-sha256", action="store_true",
