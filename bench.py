@@ -333,6 +333,16 @@ def bench_serve(args) -> dict:
         arrived = [j for j in pending if j.arrival_s <= wall]
         waiting = np.array([wall - j.arrival_s for j in arrived if j.tag not in finished])
         ok = sum(1 for r in done if r["status"] == 0)
+        by_tag = {j.tag: j for j in pending}
+        failures = []
+        for r in done:
+            if r["status"] != 0:
+                j = by_tag[r["tag"]]
+                failures.append({"status": r["status"], "kind": j.kind,
+                                 "dims": [j.lattice.nx, j.lattice.ny, j.lattice.nz], "nv": int(len(j.xyz)),
+                                 "mass_ratio": round(j.body.mass_ratio, 3), "ks0": round(j.body.ks0, 5),
+                                 "kb": round(j.body.kb, 6), "tau": round(j.lattice.tau, 3),
+                                 "steps_done": r["steps_done"]})
         # percentiles over every arrived job, the censored ones counted as waiting forever: a
         # percentile that falls on a censored job is reported as None
         n_arr = len(arrived)
@@ -342,7 +352,7 @@ def bench_serve(args) -> dict:
                 return None
             v = allt[min(n_arr - 1, int(np.ceil(q / 100.0 * n_arr)) - 1)]
             return None if not np.isfinite(v) else round(float(v), 3)
-        return {"jobs_arrived": n_arr, "jobs_finished": len(done), "ok": ok,
+        return {"jobs_arrived": n_arr, "jobs_finished": len(done), "ok": ok, "failures": failures[:40],
                 "censored": int(len(waiting)),
                 "censored_max_wait_s": round(float(waiting.max()), 2) if len(waiting) else 0.0,
                 "wall_s": round(wall, 2), "finished_per_hour": round(len(done) / wall * 3600, 1),
@@ -377,9 +387,11 @@ def bench_serve(args) -> dict:
             "config": {"workload": f"Poisson arrivals 4 jobs/s over {args.serve_window:.0f} s: "
                                    "capsule-shear and settling jobs, lattices 48^3..128x64x128, "
                                    "meshes 642-10242 vertices, 2000-10000 steps, FP16 storage, "
-                                   "32 GiB budget, up to 64 slots, 100 steps per tick; capacity from "
-                                   f"{args.serve_capacity_jobs} jobs submitted at once; plain FIFO "
-                                   f"over the first {plain_window:.0f} s of the stream"},
+                                   "32 GiB budget, up to 64 slots, 100 steps per tick"
+                                   + (f"; capacity from {args.serve_capacity_jobs} jobs submitted at once"
+                                      if cap is not None else "")
+                                   + (f"; plain FIFO over the first {plain_window:.0f} s of the stream"
+                                      if plain is not None else "")},
             "dtype": "f16-storage/f32-compute", "data": "synthetic", "n_gpus": 1}
 
 
