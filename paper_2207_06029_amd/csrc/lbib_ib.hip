@@ -260,7 +260,7 @@ __device__ __forceinline__ void store_partials(const Pools& P, const BodyDev& B,
 
 template <int NVAL>
 __device__ void fold_partials(const Pools& P, const BodyDev& B, int nblk, double* out) {
-    __shared__ double s_red[FOLD_MAX][FOLD_THREADS];
+    __shared__ double s_red[FOLD_MAX][FOLD_THREADS / 64];
     const int t = threadIdx.x;
     double acc[NVAL];
     for (int i = 0; i < NVAL; ++i) acc[i] = 0.0;
@@ -280,14 +280,22 @@ __device__ void fold_partials(const Pools& P, const BodyDev& B, int nblk, double
 #pragma unroll
                 for (int i = 0; i < NVAL; ++i) acc[i] += v[u][i];
     }
-    for (int i = 0; i < NVAL; ++i) s_red[i][t] = acc[i];
-    __syncthreads();
-    for (int w = FOLD_THREADS / 2; w >= 1; w >>= 1) {
-        if (t < w)
-            for (int i = 0; i < NVAL; ++i) s_red[i][t] += s_red[i][t + w];
-        __syncthreads();
+    // each wave sums its 64 lanes (rows by DPP, then the four rows by two exchanges), wave 0's
+    // first lane adds the waves in order: a fixed tree, so the totals are reproducible
+    const int wave = t / 64, lane = t % 64;
+#pragma unroll
+    for (int i = 0; i < NVAL; ++i) {
+        double v = gsum<16>(acc[i]);
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (lane == 0) s_red[i][wave] = v;
     }
-    for (int i = 0; i < NVAL; ++i) out[i] = s_red[i][0];
+    __syncthreads();
+    for (int i = 0; i < NVAL; ++i) {
+        double v = s_red[i][0];
+        for (int w = 1; w < FOLD_THREADS / 64; ++w) v += s_red[i][w];
+        out[i] = v;
+    }
 }
 
 // ---------------------------------------------------------------- window of a step

@@ -187,6 +187,7 @@ struct Pools {
                              // stochastic narrowing of reduced-precision storage
     int pop32;               // every job's populations span less than 4 GiB (32-bit offsets)
     int solo_job;            // job of the only body when the batch holds one body, else -1
+    int one_lattice;         // 1: the batch holds one lattice (job 0, every sweep tile its own)
     BodyDev solo_body;       // that body's record (valid when solo_job >= 0)
 };
 

@@ -454,6 +454,19 @@ __device__ __forceinline__ Win1 load_win1(const Pools& P, const JobDev& J) {
     W.fw = P.fwin + 3 * B.win_off;
     return W;
 }
+// The same for a batch of one lattice whose one body (index 0) comes with the kernel arguments:
+// the layout load does not wait for the job record.
+__device__ __forceinline__ Win1 load_win1_one(const Pools& P, const JobDev& J) {
+    Win1 W;
+    const WinDesc d = P.fdesc[0];
+    const BodyDev& B = P.solo_body;
+    const int dims[3] = {J.nx, J.ny, J.nz};
+    W.valid = win_valid(d, dims, B.win_cap, J.bc);
+    for (int a = 0; a < 3; ++a) { W.o[a] = d.o[a]; W.w[a] = d.w[a]; }
+    W.capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
+    W.fw = P.fwin + 3 * B.win_off;
+    return W;
+}
 
 // Body force at a node: uniform G plus the fixed-point immersed-boundary force of the window that
 // holds the node (one body: W; more: every body's window in turn).
@@ -628,7 +641,10 @@ __device__ __forceinline__ void sweep_node(const Pools& P, const JobDev& J, cons
     }
 }
 
-template <typename S, bool COLLIDE, int NPT, bool OFF32>
+// ONE: a batch of one lattice.  Its job (0) and body need no tile-table entry, so the job record,
+// the step counter and the force-window layout load at once, in parallel with the tile entry,
+// instead of one after the other at the start of every block.
+template <typename S, bool COLLIDE, int NPT, bool OFF32, bool ONE>
 __global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b, int xcd_chunk) {
     // The dispatcher deals consecutive blocks to the 8 XCDs in turn, each with its own L2.
     // With xcd_chunk = C > 0 the blocks are remapped so that every XCD takes C consecutive
@@ -641,13 +657,17 @@ __global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b, int xcd_chu
         if (bid < (T / span) * span) tile = (bid / span) * span + (bid & 7) * xcd_chunk + (bid >> 3) % xcd_chunk;
     }
     const int4 te = P.tiles[tile];
-    const int job = te.x;
+    const int job = ONE ? 0 : te.x;
     const JobDev& J = P.jobs[job];
     const S* src = (const S*)(a_to_b ? P.popA : P.popB) + J.pop_off;
     S* dst = (S*)(a_to_b ? P.popB : P.popA) + J.pop_off;
     const long long base = (long long)(tile - J.tile0) * blockDim.x * NPT;
     Win1 W = {};
-    if (COLLIDE && J.nbodies == 1) W = load_win1(P, J);
+    if (ONE) {
+        if (COLLIDE && P.solo_job >= 0) W = load_win1_one(P, J);
+    } else if (COLLIDE && J.nbodies == 1) {
+        W = load_win1(P, J);
+    }
     const unsigned nx = (unsigned)J.nx, ny = (unsigned)J.ny, mx = J.mx, my = J.my;
     const unsigned walls = wall_faces(J);
     // the job's step counter of the buffer being read seeds the stochastic narrowing; the block of
@@ -656,7 +676,7 @@ __global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b, int xcd_chu
     if (COLLIDE && sizeof(S) < 4) {
         const unsigned* ctr = P.sr_ctr + 2 * job;
         const unsigned c = ctr[a_to_b ? 0 : 1];
-        if (tile == J.tile0 && threadIdx.x == 0) P.sr_ctr[2 * job + (a_to_b ? 1 : 0)] = c + 1;
+        if (tile == (ONE ? 0 : J.tile0) && threadIdx.x == 0) P.sr_ctr[2 * job + (a_to_b ? 1 : 0)] = c + 1;
         seed = mix32(c + 0x632BE5ABU);
     }
 #pragma unroll
@@ -675,13 +695,13 @@ __global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b, int xcd_chu
     }
 }
 
-template <typename S, bool C, int NPT, bool OFF32>
+template <typename S, bool C, int NPT, bool OFF32, bool ONE = false>
 static void sweep_n(const Pools& P, bool a_to_b, int chunk, dim3 grid, dim3 block, hipStream_t s,
                     hipEvent_t ev0, hipEvent_t ev1) {
     if (ev0 || ev1)
-        hipExtLaunchKernelGGL((k_sweep<S, C, NPT, OFF32>), grid, block, 0, s, ev0, ev1, 0, P, (int)a_to_b, chunk);
+        hipExtLaunchKernelGGL((k_sweep<S, C, NPT, OFF32, ONE>), grid, block, 0, s, ev0, ev1, 0, P, (int)a_to_b, chunk);
     else
-        hipLaunchKernelGGL((k_sweep<S, C, NPT, OFF32>), grid, block, 0, s, P, (int)a_to_b, chunk);
+        hipLaunchKernelGGL((k_sweep<S, C, NPT, OFF32, ONE>), grid, block, 0, s, P, (int)a_to_b, chunk);
 }
 
 template <typename S, bool C, bool OFF32>
@@ -689,7 +709,11 @@ static void sweep_o(const Pools& P, bool a_to_b, int ntiles, SweepShape sh, int 
                     hipEvent_t ev0, hipEvent_t ev1) {
     dim3 grid(ntiles), block(sh.block);
     switch (sh.npt) {
-        case 1: sweep_n<S, C, 1, OFF32>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
+        case 1:
+            // a single lattice keeps one node per thread; batches may autotune to any shape
+            if (P.one_lattice) sweep_n<S, C, 1, OFF32, true>(P, a_to_b, chunk, grid, block, s, ev0, ev1);
+            else sweep_n<S, C, 1, OFF32>(P, a_to_b, chunk, grid, block, s, ev0, ev1);
+            break;
         case 2: sweep_n<S, C, 2, OFF32>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
         default: sweep_n<S, C, 4, OFF32>(P, a_to_b, chunk, grid, block, s, ev0, ev1); break;
     }

@@ -133,7 +133,7 @@ size_t workspace_need(const lbib_lattice_desc& d, long long nv, long long nt) {
     const long long nbu = (nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
     const long long nbv = (nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK, nbe = (ne + IB_BLOCK - 1) / IB_BLOCK;
     const long long capn = body ? n : 0;
-    const long long nbw = body ? std::max<long long>(1, (capn + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK) : 0;
+    const long long nbw = body ? win_blocks(capn, true) : 0;   // the larger, rigid count
     b += r(sizeof(BodyDev)) + r(4 * nbc) + r(4 * nbe) + r(4 * nbt) + r(4 * nbv) + r(4 * nbu) + r(4 * nbw);
     b += 6 * r(24 * nv);                                             // x, xprev, uv, fv, u0v, xb
     b += r(12 * nt) + r(8 * ne) + r(16 * ne) + 3 * r(8 * ne);        // tri, edge, hinge, l0, ks, theta0
@@ -413,6 +413,7 @@ lbib_status Batch::create_lattices(const std::vector<lbib_lattice_desc>& descs, 
         jobs[j].nbodies = 0;
     }
     pop_elems = off;
+    P.one_lattice = descs.size() == 1 ? 1 : 0;
     P.pop32 = 1;
     for (auto& J : jobs)
         if (19LL * J.n * storage_bytes(storage) >= (1LL << 32)) P.pop32 = 0;
@@ -553,7 +554,7 @@ lbib_status Batch::rebuild_bodies() {
         B.vbox0 = nblk_v;
         B.blk_v0 = nblk_v; B.nblk_v = nbv; nblk_v += nbv;
         B.blk_u0 = nblk_u; B.nblk_u = nbu; nblk_u += nbu;
-        const int nbw = (int)std::max<long long>(1, (capn + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
+        const int nbw = (int)win_blocks(capn, h.desc.rigid != 0);
         B.blk_w0 = nblk_w; B.nblk_w = nbw; nblk_w += nbw;
         for (int k = 0; k < nbw; ++k) bw.push_back((int)i);
         for (int k = 0; k < nbc; ++k) bc.push_back((int)i);
@@ -1011,7 +1012,7 @@ uint64_t slot_device_bytes(const SlotCaps& c, int storage) {
     const uint64_t bc = (nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, bt = (nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
     const uint64_t bu = (nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, bv = (nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK;
     const uint64_t be = (ne + IB_BLOCK - 1) / IB_BLOCK;
-    const uint64_t bw = std::max<uint64_t>(1, (win + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
+    const uint64_t bw = (uint64_t)win_blocks((long long)win, true);
     uint64_t b = 2 * 19 * nodes * es + 4 + 8 + sizeof(JobDev) + sizeof(int4) * ((nodes + per - 1) / per);
     b += sizeof(BodyDev) + 4 * (bc + be + bt + bv + bu + bw);
     b += 6 * 24 * nv + 12 * nt + 8 * ne + 16 * ne + 3 * 8 * ne;
@@ -1039,7 +1040,7 @@ lbib_status Batch::create_slotted(int nslots, const SlotCaps& c, int storage_, v
     bt_slot = (c.nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
     bu_slot = (c.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK;
     bv_slot = (c.nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK;
-    bw_slot = (int)std::max<long long>(1, (win_slot + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
+    bw_slot = (int)win_blocks(win_slot, true);
     red_slot = std::max(bc_slot, bt_slot);
     const long long S = nslots;
     // lattices: empty slots hold no job (n = 0)
@@ -1048,6 +1049,7 @@ lbib_status Batch::create_slotted(int nslots, const SlotCaps& c, int storage_, v
     ldesc.assign(nslots, lbib_lattice_desc{});
     pop_elems = S * 19 * c.nodes;
     P.pop32 = 19LL * c.nodes * (long long)es < (1LL << 32) ? 1 : 0;
+    P.one_lattice = 0;
     void* p;
     lbib_status st;
     if ((st = arena.alloc(pop_elems * es, &P.popA))) return st;
@@ -1171,7 +1173,7 @@ lbib_status Batch::slot_tables() {
         const int nbu = (B.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbv = (B.nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK;
         const int nbe = B.rigid ? 0 : (B.ne + IB_BLOCK - 1) / IB_BLOCK;
         const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
-        const int nbw = (int)std::max<long long>(1, (capn + WIN_NODES_PER_BLOCK - 1) / WIN_NODES_PER_BLOCK);
+        const int nbw = (int)win_blocks(capn, B.rigid != 0);
         B.blk_c0 = (int)bc.size(); B.nblk_c = nbc; bc.insert(bc.end(), nbc, s);
         B.blk_e0 = (int)be.size(); B.nblk_e = nbe; be.insert(be.end(), nbe, s);
         B.blk_t0 = (int)bt.size(); B.nblk_t = nbt; bt.insert(bt.end(), nbt, s);
