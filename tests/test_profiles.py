@@ -1,9 +1,10 @@
 """The profiler summaries under profiles/ stay reproducible: every one quotes the commands that
 made it, those commands run committed scripts only (no working files), bench.py's own parser
 accepts their arguments, and each counter run stays within the per-block counter limits of one
-rocprofv3 pass.  CPU only."""
+rocprofv3 pass (4 TCC, 8 SQ counters).  CPU only."""
 import glob
 import os
+import re
 import shlex
 import subprocess
 
@@ -17,7 +18,17 @@ TCC_COST = {"FETCH_SIZE": 3, "WRITE_SIZE": 2}
 
 
 def _commands(path):
-    return [ln.strip() for ln in open(path) if "rocprofv3" in ln and " -- " in ln]
+    """rocprofv3 command lines, with the shell variables the summary sets (NAME="...") expanded."""
+    env, cmds = {}, []
+    for ln in open(path):
+        ln = ln.strip()
+        m = re.fullmatch(r'([A-Z][A-Z0-9_]*)="([^"]*)"', ln)
+        if m:
+            env[m.group(1)] = m.group(2)
+        elif "rocprofv3" in ln and " -- " in ln:
+            ln = re.sub(r"\$([A-Z][A-Z0-9_]*)\b", lambda m: env.get(m.group(1), m.group(0)), ln)
+            cmds.append(ln)
+    return cmds
 
 
 def _tracked(rel):
@@ -56,3 +67,5 @@ def test_profile_commands_run_committed_files(path):
             assert names, line
             tcc = sum(TCC_COST.get(n, 1 if n.startswith("TCC_") else 0) for n in names)
             assert tcc <= 4, line
+            assert sum(n.startswith("SQ_") for n in names) <= 8, line
+            assert all(re.fullmatch(r"[A-Z][A-Za-z0-9_]*", n) for n in names), line
