@@ -244,18 +244,24 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
 }
 
 // Deterministic per-body totals.  Every block of a body stores its partial sums (up to six
-// values, in a slot of 16 doubles); one block per body folds them in a later launch, whose
-// boundary makes the partials visible without a per-block device-scope release (each of which
-// would write back an L2).  Thread t takes blocks t, t+512, ... in order, then a fixed-shape
-// tree in LDS combines the 512 results: the order depends only on the body's own block count,
-// so totals are bitwise reproducible and independent of other jobs in the launch.
+// values, one row per value in the body's region); one block per body folds them in a later
+// launch, whose boundary makes the partials visible without a per-block device-scope release
+// (each of which would write back an L2).  Thread t takes blocks t, t+512, ... in order, then a
+// fixed tree (DPP within each wave, the eight waves in order) combines the 512 results: the
+// order depends only on the body's own block count, so totals are bitwise reproducible and
+// independent of other jobs in the launch.
 constexpr int FOLD_MAX = 6;
 constexpr int FOLD_THREADS = 512;   // threads of the fold block: 2048 partials per load round
 
+// A body's partials: value i of block k at 16 red_slot + i stride + k, stride = the body's larger
+// block count (its region holds 16 such rows), so a wave of the fold reads value i of 64
+// consecutive blocks from consecutive addresses.
+__device__ __forceinline__ long long partial_stride(const BodyDev& B) { return max(B.nblk_c, B.nblk_t); }
 __device__ __forceinline__ void store_partials(const Pools& P, const BodyDev& B, int blk, const double* v,
                                                int nval) {
-    double* slot = P.partial + 16LL * (B.red_slot + blk);
-    for (int i = 0; i < nval; ++i) slot[i] = v[i];
+    double* row = P.partial + 16LL * B.red_slot + blk;
+    const long long st = partial_stride(B);
+    for (int i = 0; i < nval; ++i) row[i * st] = v[i];
 }
 
 template <int NVAL>
@@ -265,14 +271,16 @@ __device__ void fold_partials(const Pools& P, const BodyDev& B, int nblk, double
     double acc[NVAL];
     for (int i = 0; i < NVAL; ++i) acc[i] = 0.0;
     // four slots per round, loaded together; summed in ascending block order
+    const double* rows = P.partial + 16LL * B.red_slot;
+    const long long st = partial_stride(B);
     for (int k0 = t; k0 < nblk; k0 += 4 * FOLD_THREADS) {
         double v[4][NVAL];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = k0 + u * FOLD_THREADS;
-            const double* slot = P.partial + 16LL * (B.red_slot + (k < nblk ? k : 0));
+            const double* col = rows + (k < nblk ? k : 0);
 #pragma unroll
-            for (int i = 0; i < NVAL; ++i) v[u][i] = slot[i];
+            for (int i = 0; i < NVAL; ++i) v[u][i] = col[i * st];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
