@@ -338,7 +338,7 @@ def bench_serve(args) -> dict:
         for r in done:
             if r["status"] != 0:
                 j = by_tag[r["tag"]]
-                failures.append({"status": r["status"], "kind": j.kind,
+                failures.append({"tag": int(r["tag"]), "status": r["status"], "kind": j.kind,
                                  "dims": [j.lattice.nx, j.lattice.ny, j.lattice.nz], "nv": int(len(j.xyz)),
                                  "mass_ratio": round(j.body.mass_ratio, 3), "ks0": round(j.body.ks0, 5),
                                  "kb": round(j.body.kb, 6), "tau": round(j.lattice.tau, 3),

@@ -85,6 +85,17 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, __half v, unsig
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, __hip_bfloat16 v, unsigned voff, unsigned soff) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, 0);
 }
+// Loads of one stored value, in storage units, through the same kind of resource.
+template <typename S> __device__ __forceinline__ float buf_ld_raw(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <> __device__ __forceinline__ float buf_ld_raw<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ float buf_ld_raw<__half>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0)));
+}
+template <> __device__ __forceinline__ float buf_ld_raw<__hip_bfloat16>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __uint_as_float((unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0) << 16);
+}
 
 // Counter-based random offsets of one node and step: a 32-bit integer hash (multiply-xorshift) of
 // the node index and the job's step counter, continued by one xorshift step; its eight bytes give
@@ -325,6 +336,30 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J,
     const int dxm = (lx & !oxm) ? nx - 1 : -1, dxp = (hx & !oxp) ? 1 - nx : 1;
     const int dym = (ly & !oym) ? (ny - 1) * sy : -sy, dyp = (hy & !oyp) ? (1 - ny) * sy : sy;
     const int dzm = (lz & !ozm) ? (nz - 1) * sz : -sz, dzp = (hz & !ozp) ? (1 - nz) * sz : sz;
+    // Waves whose nodes all lie away from the y and z faces: the y and z parts of every source
+    // shift are the same on every lane, so a stream without an x part loads at the node's own
+    // offset with the shift in a scalar register, and a stream with one adds only the lane's x
+    // part (the periodic wrap, or the wall redirect, at x = 0 and x = nx - 1).  Same addresses,
+    // same values as the general form below.
+    if (OFF32 && __all(y > 0 && y < ny - 1 && z > 0 && z < nz - 1)) {
+        const unsigned pb = (unsigned)N * (unsigned)sizeof(S), kb = (unsigned)k * (unsigned)sizeof(S);
+        const __amdgpu_buffer_rsrc_t rs = pop_rsrc((void*)src, Q * pb);
+        const unsigned kxm = kb + (unsigned)(dxm * (int)sizeof(S)), kxp = kb + (unsigned)(dxp * (int)sizeof(S));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int e0 = cx(i), e1 = cy(i), e2 = cz(i);
+            const unsigned syz = (unsigned)i * pb - (unsigned)((e1 * sy + e2 * sz) * (int)sizeof(S));
+            float v;
+            if (e0 == 0) {
+                v = buf_ld_raw<S>(rs, kb, syz);
+            } else {
+                const bool o = e0 == 1 ? oxm : oxp;
+                const unsigned alt = (unsigned)opp(i) * pb + kb, nrm = (e0 == 1 ? kxm : kxp) + syz;
+                v = buf_ld_raw<S>(rs, o ? alt : nrm, 0u);
+            }
+            g[i] = RAW ? v : v * (1.0f / Codec<S>::scale);
+        }
+    } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int e0 = cx(i), e1 = cy(i), e2 = cz(i);
@@ -347,6 +382,7 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J,
             const long long idx = o ? (long long)opp(i) * N + k : (long long)i * N + k + d;
             g[i] = RAW ? Codec<S>::raw(src + idx) : Codec<S>::ld(src + idx);
         }
+    }
     }
     if (!(walls & WALL_TERMS) || !(oxm || oxp || oym || oyp || ozm || ozp)) return;
     // the wall terms are formed on deviations (exact power-of-two rescaling of raw values)

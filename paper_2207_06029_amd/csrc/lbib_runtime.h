@@ -22,11 +22,13 @@ constexpr int WS_MAX_VALENCE = 12;
 size_t workspace_need(const lbib_lattice_desc& d, long long nv, long long nt);
 // Force-window capacity per axis for a body of bounding radius rbound about its vertex mean.
 void window_capacity(const int dims[3], bool rigid, double rbound, int cap[3]);
-// Window-moments blocks of a body of window capacity capn.  A rigid body's window stays at its
-// capacity (the box only moves), so it gets one 256-thread block per 256 capacity nodes, a node
-// per thread.  A membrane's capacity allows 2.5 times its rest extent per axis, about fifteen
-// times the volume of its current window, so a block per WIN_NODES_PER_BLOCK capacity nodes
-// still gives each thread about one node of the window.
+// Window-moments blocks of such a body (its B.nblk_w).
+long long window_blocks(const int dims[3], bool rigid, double rbound);
+// Window-moments blocks for a window of capn nodes.  A rigid body's window stays at its
+// capacity (the box only moves), so it gets one 256-thread block per 256 nodes, a node per thread.
+// A membrane gets one block per WIN_NODES_PER_BLOCK nodes of the window it usually spans (2.5
+// times its rest extent per axis), about fifteen times the volume of its current window, so each
+// thread still has about one node of it; the blocks stride over larger windows.
 constexpr int WIN_NODES_PER_BLOCK_RIGID = 256;
 inline long long win_blocks(long long capn, bool rigid) {
     const long long per = rigid ? WIN_NODES_PER_BLOCK_RIGID : WIN_NODES_PER_BLOCK;

@@ -146,12 +146,22 @@ size_t workspace_need(const lbib_lattice_desc& d, long long nv, long long nt) {
 }
 
 void window_capacity(const int dims[3], bool rigid, double rbound, int cap[3]) {
-    // membranes may stretch to 2.5 times their rest extent (a Taylor deformation near 0.6 at
-    // fixed volume) before the window overflows; rigid bodies only carry their box along.  Only
-    // memory scales with the capacity: kernels cover the current window.
-    const double grow = rigid ? 1.0 : 2.5;
+    // rigid bodies only carry their box along.  A membrane's window may grow to the whole lattice:
+    // a soft capsule at a high capillary number can keep elongating in shear (a fixed bound of
+    // 2.5 times the rest extent ended such jobs with a window error).  Only memory scales with
+    // the capacity (40 B per node): kernels cover the current window.
     for (int a = 0; a < 3; ++a)
-        cap[a] = std::min(dims[a], (int)std::ceil(2.0 * grow * rbound) + 2 * WIN_MARGIN + 4);
+        cap[a] = rigid ? std::min(dims[a], (int)std::ceil(2.0 * rbound) + 2 * WIN_MARGIN + 4) : dims[a];
+}
+
+long long window_blocks(const int dims[3], bool rigid, double rbound) {
+    // the window a membrane usually spans: 2.5 times its rest extent per axis (a Taylor
+    // deformation near 0.6 at fixed volume); larger windows are covered by the same blocks
+    const double grow = rigid ? 1.0 : 2.5;
+    long long n = 1;
+    for (int a = 0; a < 3; ++a)
+        n *= std::min(dims[a], (int)std::ceil(2.0 * grow * rbound) + 2 * WIN_MARGIN + 4);
+    return win_blocks(n, rigid);
 }
 
 // ---------------------------------------------------------------- body rest state
@@ -496,6 +506,7 @@ void body_record(const HostBody& h, const JobDev& J, BodyDev& B) {
     for (int k = 0; k < 9; ++k) B.Ib[k] = h.Ib[k];
     const int dims[3] = {J.nx, J.ny, J.nz};
     window_capacity(dims, h.desc.rigid != 0, h.rbound, B.win_cap);
+    B.nblk_w = (int)window_blocks(dims, h.desc.rigid != 0, h.rbound);
 }
 
 // Append body h's incidence lists padded to widths wt (triangles) and wh (hinge roles), -1 past
@@ -554,8 +565,8 @@ lbib_status Batch::rebuild_bodies() {
         B.vbox0 = nblk_v;
         B.blk_v0 = nblk_v; B.nblk_v = nbv; nblk_v += nbv;
         B.blk_u0 = nblk_u; B.nblk_u = nbu; nblk_u += nbu;
-        const int nbw = (int)win_blocks(capn, h.desc.rigid != 0);
-        B.blk_w0 = nblk_w; B.nblk_w = nbw; nblk_w += nbw;
+        const int nbw = B.nblk_w;   // from body_record
+        B.blk_w0 = nblk_w; nblk_w += nbw;
         for (int k = 0; k < nbw; ++k) bw.push_back((int)i);
         for (int k = 0; k < nbc; ++k) bc.push_back((int)i);
         for (int k = 0; k < nbe; ++k) be.push_back((int)i);
@@ -1172,14 +1183,13 @@ lbib_status Batch::slot_tables() {
         const int nbc = (B.nt + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbt = (B.nt + TRI_PER_BLOCK - 1) / TRI_PER_BLOCK;
         const int nbu = (B.nv + MLS_PER_BLOCK - 1) / MLS_PER_BLOCK, nbv = (B.nv + VERT_PER_BLOCK - 1) / VERT_PER_BLOCK;
         const int nbe = B.rigid ? 0 : (B.ne + IB_BLOCK - 1) / IB_BLOCK;
-        const long long capn = (long long)B.win_cap[0] * B.win_cap[1] * B.win_cap[2];
-        const int nbw = (int)win_blocks(capn, B.rigid != 0);
+        const int nbw = B.nblk_w;   // from body_record at admission
         B.blk_c0 = (int)bc.size(); B.nblk_c = nbc; bc.insert(bc.end(), nbc, s);
         B.blk_e0 = (int)be.size(); B.nblk_e = nbe; be.insert(be.end(), nbe, s);
         B.blk_t0 = (int)bt.size(); B.nblk_t = nbt; bt.insert(bt.end(), nbt, s);
         B.blk_v0 = (int)bv.size(); B.nblk_v = nbv; bv.insert(bv.end(), nbv, s);
         B.blk_u0 = (int)bu.size(); B.nblk_u = nbu; bu.insert(bu.end(), nbu, s);
-        B.blk_w0 = (int)bw.size(); B.nblk_w = nbw; bw.insert(bw.end(), nbw, s);
+        B.blk_w0 = (int)bw.size(); bw.insert(bw.end(), nbw, s);
     }
     auto put = [&](const std::vector<int>& v, const int* dst) -> lbib_status {
         if (!v.empty()) HIP_TRY(hipMemcpyAsync((void*)dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, stream));
