@@ -321,7 +321,7 @@ __device__ __forceinline__ unsigned wall_faces(const JobDev& J) {
 // the loads have returned.  Without ZH_CLOSURE the populations of Zou-He wall nodes stay
 // unclosed (finite but meaningless): for readers that never look at those nodes.
 
-template <typename S, bool ZH_CLOSURE = true, bool OFF32 = false, bool RAW = false>
+template <typename S, bool ZH_CLOSURE = true, bool OFF32 = false, bool RAW = false, bool YZ_FAST = false>
 __device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J, int x, int y,
                                      int z, long long k, float g[Q], unsigned walls) {
     const long long N = J.n;
@@ -341,7 +341,7 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, const JobDev& J,
     // offset with the shift in a scalar register, and a stream with one adds only the lane's x
     // part (the periodic wrap, or the wall redirect, at x = 0 and x = nx - 1).  Same addresses,
     // same values as the general form below.
-    if (OFF32 && __all(y > 0 && y < ny - 1 && z > 0 && z < nz - 1)) {
+    if (OFF32 && YZ_FAST && __all(y > 0 && y < ny - 1 && z > 0 && z < nz - 1)) {
         const unsigned pb = (unsigned)N * (unsigned)sizeof(S), kb = (unsigned)k * (unsigned)sizeof(S);
         const __amdgpu_buffer_rsrc_t rs = pop_rsrc((void*)src, Q * pb);
         const unsigned kxm = kb + (unsigned)(dxm * (int)sizeof(S)), kxp = kb + (unsigned)(dxp * (int)sizeof(S));
@@ -587,12 +587,12 @@ __device__ __forceinline__ void bgk_guo(const float g[Q], float drho, float rho,
 // store.  With COLLIDE false the pulled values are stored unchanged (pure streaming).  Stores go to
 // the population planes through a 32-bit byte offset of the node (the same for every plane).
 // Populations stay in storage units from load to store; the moments are scaled back exactly.
-template <typename S, bool COLLIDE, bool OFF32>
+template <typename S, bool COLLIDE, bool OFF32, bool YZ_FAST>
 __device__ __forceinline__ void sweep_node(const Pools& P, const JobDev& J, const Win1& W,
                                            const S* __restrict__ src, S* __restrict__ dst, long long k,
                                            int x, int y, int z, int job, unsigned seed, unsigned walls) {
     float g[Q];
-    pull<S, true, OFF32, true>(src, J, x, y, z, k, g, walls);
+    pull<S, true, OFF32, true, YZ_FAST>(src, J, x, y, z, k, g, walls);
     const long long N = J.n;
     const unsigned kb = (unsigned)k * (unsigned)sizeof(S);
     const long long pb = N * (long long)sizeof(S);   // bytes per population plane
@@ -726,7 +726,9 @@ __global__ void __launch_bounds__(1024) k_sweep(Pools P, int a_to_b, int xcd_chu
         const unsigned qx = mx ? __umulhi(xs, mx) : xs / nx;
         const unsigned ys = y0 + qx;
         const unsigned qy = my ? __umulhi(ys, my) : ys / ny;
-        sweep_node<S, COLLIDE, OFF32>(P, J, W, src, dst, k, (int)(xs - qx * nx), (int)(ys - qy * ny), (int)(z0 + qy),
+        // the scalar-shift pull only in the one-node-per-thread form: unrolled over several
+        // nodes per thread its second code path made those forms slower
+        sweep_node<S, COLLIDE, OFF32, NPT == 1>(P, J, W, src, dst, k, (int)(xs - qx * nx), (int)(ys - qy * ny), (int)(z0 + qy),
                                job, seed, walls);
     }
 }
