@@ -482,8 +482,9 @@ __device__ __forceinline__ void spread_block(const Pools& P, const JobDev& J, co
 }
 
 // ---------------------------------------------------------------- centroids (+ hinges)
+// Batched launches ask for four waves per SIMD, as the probe kernel does (128 VGPRs, a 52 B spill).
 template <bool SOLO, int G>
-__global__ void __launch_bounds__(IB_BLOCK) k_centroids(Pools P, int nblk_tri, int fold) {
+__global__ void __launch_bounds__(IB_BLOCK, SOLO ? 1 : 4) k_centroids(Pools P, int nblk_tri, int fold) {
     constexpr int MLS_NODES = MlsLane<G>::N, MLS_PER_BLOCK = IB_BLOCK / G;
     if ((int)blockIdx.x >= nblk_tri) {
         // edge blocks: one thread per hinge of a membrane
@@ -563,8 +564,11 @@ __global__ void __launch_bounds__(IB_BLOCK) k_centroids(Pools P, int nblk_tri, i
         mls_setup<G>(J, cen, B.rw2, lane, m, err);
         for (int a = 0; a < 3; ++a) cen_node[a] = (int)floor(cen[a] + 0.5);
         float4 mom[MLS_NODES];
-        mls_moments<G>(P, J, B, md, m, mom, err);
+        // a lone body's launch is a latency chain: its moment loads go out before the solve; a
+        // batched launch is throughput-bound and loads them after it, to hold fewer registers
+        if (SOLO) mls_moments<G>(P, J, B, md, m, mom, err);
         mls_solve<G>(m, B.wq, false, err);
+        if (!SOLO) mls_moments<G>(P, J, B, md, m, mom, err);
         const double U0 = group_dot<G>(m.phi, 1, mom, 1);
         const double U1 = group_dot<G>(m.phi, 1, mom, 2);
         const double U2 = group_dot<G>(m.phi, 1, mom, 3);

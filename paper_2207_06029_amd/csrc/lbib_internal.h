@@ -31,7 +31,8 @@ constexpr int VERT_GROUP = 16;
 constexpr int VERT_BLOCK = 256;
 constexpr int VERT_PER_BLOCK = VERT_BLOCK / VERT_GROUP;
 constexpr int MAX_RED_BLOCKS = 65536;
-// window-moments blocks per body: one 256-thread block per this many nodes of window capacity
+// window-moments blocks of a membrane: one 256-thread block per this many nodes of the window it
+// usually spans (rigid bodies: one per 256 nodes, see win_blocks)
 constexpr int WIN_NODES_PER_BLOCK = 2048;
 
 // error flag bits (per job)
