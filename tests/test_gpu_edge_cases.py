@@ -95,6 +95,28 @@ def test_body_driven_into_a_wall_reports_domain_error(api):
     assert ei.value.code == -7
 
 
+def test_soft_capsule_grows_past_two_and_a_half_rest_extents(api):
+    """A very soft capsule (Ca near 0.5) keeps elongating in the shear flow of a 96x48x96 channel:
+    after 8980 steps it spans more than 2.5 times its rest diameter along the flow.  A membrane's
+    force window may span the lattice, so the job runs to its end without a window error."""
+    tau, u_wall, radius = 0.683, 0.01, 9.6
+    spec = I.LatticeSpec(96, 48, 96, tau, storage=I.STORE_F16, **I.shear_walls(u_wall))
+    lat = api.Lattice(spec)
+    xyz, tri = I.spheroid_mesh(4, (radius, radius, radius), (47.5, 23.5, 47.5))
+    ks0 = 5.31e-4
+    body = I.BodySpec(rigid=0, ks0=ks0, kb=0.0226 * ks0, kv=0.0, mass_ratio=1.533)
+    b = lat.add_body(body, xyz, tri)
+    for _ in range(8):
+        lat.step(1000)
+        lat.sync()
+    lat.step(980)
+    x, _ = lat.body_state(b)
+    ext = x.max(axis=0) - x.min(axis=0)
+    print(f"extent after 8980 steps: {np.round(ext, 2)} (rest diameter {2 * radius})")
+    assert np.all(np.isfinite(x))
+    assert ext[0] > 2.5 * 2 * radius
+
+
 def test_batch_with_fluid_only_job_alone_vs_mix_bitwise(api):
     jobs = I.capsule_batch(seed=5, njobs=2, storage=I.STORE_F16, steps=60)
     fluid = I.LatticeSpec(24, 20, 16, 0.9, storage=I.STORE_F16, **I.shear_walls(0.01))
