@@ -68,8 +68,10 @@ typedef enum {
 typedef enum { LBIB_BC_PERIODIC = 0, LBIB_BC_ZOUHE_VELOCITY = 1, LBIB_BC_BOUNCEBACK = 2 } lbib_bc;
 
 /* Population storage.  All forms store the deviation g_i = f_i - w_i from the lattice
- * weights and collide in FP32; FP16/BF16 narrow with round-to-nearest-even and keep
- * subnormals.  FP16 holds g_i * 2^12 (an exact power-of-two scale that keeps small deviations
+ * weights and collide in FP32.  FP16/BF16 keep subnormals; the step's stores narrow with
+ * stochastic rounding (dither offsets from a counter-based hash of node index and step, so a
+ * job's results are reproducible and the same alone or in a batch), initialisation and the
+ * setters with round-to-nearest-even.  FP16 holds g_i * 2^12 (an exact power-of-two scale that keeps small deviations
  * in the normal range) and is the reduced-precision form: it stays within 1e-3 (relative L2 of
  * the velocity) of the FP64 scheme.  BF16 holds g_i; its 8 significand bits do NOT meet that
  * bound (about 2e-2 on a sheared box after 300 steps) and it is kept for bandwidth studies
