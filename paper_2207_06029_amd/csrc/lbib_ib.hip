@@ -636,11 +636,11 @@ __device__ void vertex_velocity_block(const Pools& P, int vb) {
 // ---------------------------------------------------------------- triangles (probes)
 // Group 2k evaluates the outer probe of triangle k of the block, group 2k+1 the inner one.
 // Blocks from nblk_tri on compute the vertex velocities instead.
-// Batched launches (many bodies, throughput-bound) ask for four waves per SIMD: the compiler fits
-// the kernel in 128 VGPRs with a 20 B spill, and the batched step gains more than that costs.
-// A lone body's launch is a latency chain and keeps its registers.
+// Four waves per SIMD: the compiler fits the kernel in 128 VGPRs (the batched form with a 20 B
+// spill).  Batched launches are throughput-bound and gain the most; a lone body's launch gains
+// where its markers outnumber a round of the chip (256x128x256), and loses nothing below.
 template <bool SOLO, int G>
-__global__ void __launch_bounds__(IB_BLOCK, SOLO ? 1 : 4) k_triangles(Pools P, int nblk_tri) {
+__global__ void __launch_bounds__(IB_BLOCK, 4) k_triangles(Pools P, int nblk_tri) {
     constexpr int MLS_NODES = MlsLane<G>::N, MLS_PER_BLOCK = IB_BLOCK / G, TRI_PER_BLOCK = MLS_PER_BLOCK / 2;
     if ((int)blockIdx.x >= nblk_tri) {
         vertex_velocity_block<SOLO, G>(P, blockIdx.x - nblk_tri);
